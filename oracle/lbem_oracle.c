@@ -1,0 +1,461 @@
+/*
+ * lbem_oracle.c -- plain, slow, FP64 reference implementation of the
+ * pseudo-vector lattice-BGK scheme for Maxwell's equations in heterogeneous
+ * media (Hanasoge, Succi & Orszag, "Lattice Boltzmann Method for
+ * Electromagnetic Wave Propagation", arXiv:1108.2651).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code with the HIP path.
+ *
+ * Each population carries the FULL D x D tensor g_{i,alpha,beta} (diagonal
+ * and both triangles), exactly as the paper writes it (Section "Lattice BGK
+ * formulation"), with no reduction to pseudo-vector components, no fusion
+ * and no blocking.  One time step is: moments -> equilibrium -> source ->
+ * BGK collision (eq. COLLI) -> streaming (eq. STREAM) into a second buffer.
+ *
+ * Readings of the paper taken here (listed with reasons in the design notes):
+ *  - c^2 in the equilibrium is the per-axis second moment of the weights,
+ *    c_L^2 = sum_i w_i c_{i,gamma}^2 = (1-w0)/D (the 6+1 example of the
+ *    lattice section fixes the per-axis meaning).
+ *  - The magnetic field entering the equilibrium is Bbar = K/(D-1), with
+ *    K_beta = sum_alpha sum_i c_{i,alpha} g_{i,alpha,beta}: eq. relate.2
+ *    puts each B_beta into (D-1) first moments; Bbar is their symmetric
+ *    mean.  The physical field reported is B = K and the Maxwell speed is
+ *    c_M^2 = c_L^2/(D-1) (identical readings in 2D, where D-1 = 1).
+ *  - The medium: c_L^2(x) = (1 - w0_vac)/(D eps_r mu_r), i.e. the rest
+ *    weight w0(x) = 1 - D c_L^2(x) realises the local light speed
+ *    (weights of the lattice section); w0 must lie in [0,1).
+ *  - Source S_gamma = c_M^2 eps_{gamma,beta,kappa} B_beta d_kappa ln mu
+ *    - j_gamma/eps_abs (Maxwell section; the polarisation convolution is
+ *    omitted as the paper itself does), eps_abs = eps_r/c_vac^2, the
+ *    gradient by periodic central differences.
+ *  - Macroscopic variables come from the plain pre-collision sums; the
+ *    source of step t uses B(t) and j(x,t); initial populations are the
+ *    equilibrium of the initial fields.
+ *  - 3D velocity order 0,+x,+y,+z,-x,-y,-z; 2D order of the paper
+ *    (0,(1,0),(0,1),(-1,0),(0,-1)).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EUNSTABLE (-3)
+#define ORC_ESTATE (-6)
+
+typedef struct {
+    int D, Q;
+    long nx, ny, nz, n;
+    double tau, w0_vac;
+    int c[7][3];          /* lattice velocities c_{i,alpha} */
+    double *cL2;          /* per-axis lattice c^2 (the paper's c^2) */
+    double *w0;           /* rest weight */
+    double *eps_abs;      /* absolute permittivity (vacuum mu = 1) */
+    double *mu_r;         /* relative permeability */
+    double *dlnmu;        /* [3][n] central-difference gradient of ln mu */
+    double *g, *gs;       /* [n][Q][D][D] populations, streamed copy */
+    double *jd;           /* [3][n] current-density footprint (weights) */
+    long t;
+    int have_medium, have_fields, has_mu;
+} orc_t;
+
+/* Levi-Civita symbol over three indices. */
+static int levi(int a, int b, int c)
+{
+    if (a == b || b == c || a == c) return 0;
+    if ((a == 0 && b == 1 && c == 2) || (a == 1 && b == 2 && c == 0) ||
+        (a == 2 && b == 0 && c == 1))
+        return 1;
+    return -1;
+}
+
+static void velocities(int D, int c[7][3])
+{
+    memset(c, 0, sizeof(int) * 21);
+    if (D == 2) {
+        /* counter-clockwise order of the lattice section */
+        c[1][0] = 1; c[2][1] = 1; c[3][0] = -1; c[4][1] = -1;
+    } else {
+        c[1][0] = 1; c[2][1] = 1; c[3][2] = 1;
+        c[4][0] = -1; c[5][1] = -1; c[6][2] = -1;
+    }
+}
+
+static double weight(int i, double w0, int D)
+{
+    /* rest particle w0, moving particles (1-w0)/(2D) */
+    return i == 0 ? w0 : (1.0 - w0) / (2.0 * D);
+}
+
+static long wrap(long v, long n) { v %= n; return v < 0 ? v + n : v; }
+
+static long neighbour(const orc_t* o, long x, const int* d, int sign)
+{
+    long ix = x % o->nx, iy = (x / o->nx) % o->ny, iz = x / (o->nx * o->ny);
+    ix = wrap(ix + sign * d[0], o->nx);
+    iy = wrap(iy + sign * d[1], o->ny);
+    iz = wrap(iz + sign * d[2], o->nz);
+    return ix + o->nx * (iy + o->ny * iz);
+}
+
+#define GI(o, x, i, a, b) ((((size_t)(x) * (o)->Q + (i)) * (o)->D + (a)) * (o)->D + (b))
+
+/* ------------------------------------------------------------------------
+ * Equilibrium of eq. distrib.func:
+ *   g0_{i,a,b} = (w_i/c^2) [ Lambda_{a,b} + c_{i,a} Bbar_b - c_{i,b} Bbar_a ]
+ * The wedge term is evaluated as one difference so that the result is
+ * exactly antisymmetric in (a,b) under IEEE arithmetic.
+ * ------------------------------------------------------------------------ */
+static void equilibrium(int D, const int c[7][3], double w0, double cl2,
+                        const double* Lam, const double* Bbar, double* out)
+{
+    int Q = 2 * D + 1;
+    for (int i = 0; i < Q; ++i) {
+        double wc = weight(i, w0, D) / cl2;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                double wedge = c[i][a] * Bbar[b] - c[i][b] * Bbar[a];
+                out[(i * D + a) * D + b] = wc * (Lam[a * D + b] + wedge);
+            }
+    }
+}
+
+/* Moments of one cell: rho_{ab} = sum_i g_iab (relate.1 before scaling),
+ * K_b = sum_a sum_i c_ia g_iab (contracted first moment, relate.2). */
+static void moments(int D, const int c[7][3], const double* gc, double* rho, double* K)
+{
+    int Q = 2 * D + 1;
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < Q; ++i) s += gc[(i * D + a) * D + b];
+            rho[a * D + b] = s;
+        }
+    for (int b = 0; b < D; ++b) {
+        double s = 0.0;
+        for (int a = 0; a < D; ++a)
+            for (int i = 0; i < Q; ++i) s += c[i][a] * gc[(i * D + a) * D + b];
+        K[b] = s;
+    }
+}
+
+/* E_gamma = -1/2 eps_{gamma a b} Lambda_{ab} (Levi-Civita recovery). */
+static void efield(int D, const double* Lam, double* E)
+{
+    for (int gm = 0; gm < 3; ++gm) {
+        double s = 0.0;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) s += levi(gm, a, b) * Lam[a * D + b];
+        E[gm] = -0.5 * s;
+    }
+}
+
+/* One cell's collision (eq. COLLI) with tensor source
+ * T_{i,a,b} = -(w_i/c^2) eps_{gamma a b} S_gamma. */
+static void collide_cell(int D, const int c[7][3], double w0, double cl2, double tau,
+                         const double* gc, const double* S, double* out)
+{
+    int Q = 2 * D + 1;
+    double rho[9], K[3], Lam[9], Bbar[3], geq[63];
+    moments(D, c, gc, rho, K);
+    for (int k = 0; k < D * D; ++k) Lam[k] = cl2 * rho[k];
+    for (int b = 0; b < D; ++b) Bbar[b] = K[b] / (double)(D - 1);
+    equilibrium(D, c, w0, cl2, Lam, Bbar, geq);
+    double om = 1.0 / tau;
+    for (int i = 0; i < Q; ++i) {
+        double wc = weight(i, w0, D) / cl2;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                double es = 0.0;
+                for (int gm = 0; gm < 3; ++gm) es += levi(gm, a, b) * S[gm];
+                double T = -wc * es;
+                int k = (i * D + a) * D + b;
+                out[k] = (1.0 - om) * gc[k] + om * geq[k] + T;
+            }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+
+orc_t* orc_create(int D, long nx, long ny, long nz, double tau, double w0_vac)
+{
+    if ((D != 2 && D != 3) || nx < 1 || ny < 1 || nz < 1 || (D == 2 && nz != 1))
+        return NULL;
+    if (!(tau > 0.0) || !(w0_vac >= 0.0 && w0_vac < 1.0)) return NULL;
+    orc_t* o = (orc_t*)calloc(1, sizeof(orc_t));
+    if (!o) return NULL;
+    o->D = D; o->Q = 2 * D + 1;
+    o->nx = nx; o->ny = ny; o->nz = nz; o->n = nx * ny * nz;
+    o->tau = tau; o->w0_vac = w0_vac;
+    velocities(D, o->c);
+    size_t n = (size_t)o->n, pop = n * o->Q * D * D;
+    o->cL2 = (double*)calloc(n, sizeof(double));
+    o->w0 = (double*)calloc(n, sizeof(double));
+    o->eps_abs = (double*)calloc(n, sizeof(double));
+    o->mu_r = (double*)calloc(n, sizeof(double));
+    o->dlnmu = (double*)calloc(3 * n, sizeof(double));
+    o->g = (double*)calloc(pop, sizeof(double));
+    o->gs = (double*)calloc(pop, sizeof(double));
+    o->jd = (double*)calloc(3 * n, sizeof(double));
+    if (!o->cL2 || !o->w0 || !o->eps_abs || !o->mu_r || !o->dlnmu || !o->g || !o->gs ||
+        !o->jd) {
+        free(o->cL2); free(o->w0); free(o->eps_abs); free(o->mu_r); free(o->dlnmu);
+        free(o->g); free(o->gs); free(o->jd); free(o);
+        return NULL;
+    }
+    return o;
+}
+
+void orc_destroy(orc_t* o)
+{
+    if (!o) return;
+    free(o->cL2); free(o->w0); free(o->eps_abs); free(o->mu_r); free(o->dlnmu);
+    free(o->g); free(o->gs); free(o->jd); free(o);
+}
+
+int orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+    return omp_get_max_threads();
+#else
+    (void)k;
+    return 1;
+#endif
+}
+
+/* Medium: c_L^2 = (1-w0_vac)/(D eps_r mu_r); w0 = 1 - D c_L^2 in [0,1). */
+int orc_set_medium(orc_t* o, const double* eps_r, const double* mu_r)
+{
+    int D = o->D;
+    double cvac2 = (1.0 - o->w0_vac) / (double)(D * (D - 1));
+    o->has_mu = 0;
+    for (long x = 0; x < o->n; ++x) {
+        double e = eps_r[x], m = mu_r ? mu_r[x] : 1.0;
+        if (!(e > 0.0) || !(m > 0.0) || !isfinite(e) || !isfinite(m)) return ORC_EINVAL;
+        double cl2 = (1.0 - o->w0_vac) / ((double)D * e * m);
+        double w0 = 1.0 - D * cl2;
+        if (!(w0 >= 0.0 && w0 < 1.0)) return ORC_EUNSTABLE;
+        o->cL2[x] = cl2;
+        o->w0[x] = w0;
+        o->eps_abs[x] = e / cvac2;
+        o->mu_r[x] = m;
+        if (m != 1.0) o->has_mu = 1;
+    }
+    for (long x = 0; x < o->n; ++x)
+        for (int k = 0; k < 3; ++k) {
+            int d[3] = {0, 0, 0};
+            d[k] = 1;
+            if (k >= D) { o->dlnmu[k * o->n + x] = 0.0; continue; }
+            long xp = neighbour(o, x, d, +1), xm = neighbour(o, x, d, -1);
+            o->dlnmu[k * o->n + x] = 0.5 * (log(o->mu_r[xp]) - log(o->mu_r[xm]));
+        }
+    o->have_medium = 1;
+    return ORC_OK;
+}
+
+/* Initial populations: equilibrium of E0, B0 with Lambda_ab = -eps_{gab} E_g. */
+int orc_init_fields(orc_t* o, const double* E, const double* B)
+{
+    if (!o->have_medium) return ORC_ESTATE;
+    int D = o->D;
+    long n = o->n;
+    for (long x = 0; x < n; ++x) {
+        double Lam[9], Bbar[3];
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                double s = 0.0;
+                for (int gm = 0; gm < 3; ++gm) s += levi(gm, a, b) * E[gm * n + x];
+                Lam[a * D + b] = -s;
+            }
+        for (int b = 0; b < D; ++b) Bbar[b] = B[b * n + x] / (double)(D - 1);
+        equilibrium(D, o->c, o->w0[x], o->cL2[x], Lam, Bbar, &o->g[GI(o, x, 0, 0, 0)]);
+    }
+    o->t = 0;
+    o->have_fields = 1;
+    return ORC_OK;
+}
+
+/* Current footprint: j_comp(cell) += weight (amplitude series given per step). */
+int orc_set_source(orc_t* o, long m, const int* comp, const long* cell, const double* weight)
+{
+    memset(o->jd, 0, sizeof(double) * 3 * o->n);
+    for (long k = 0; k < m; ++k) {
+        if (comp[k] < 0 || comp[k] > 2 || cell[k] < 0 || cell[k] >= o->n) return ORC_EINVAL;
+        if (o->D == 2 && comp[k] != 2) return ORC_EINVAL;
+        o->jd[comp[k] * o->n + cell[k]] += weight[k];
+    }
+    return ORC_OK;
+}
+
+/* Pre-collision macroscopic fields of one cell (E, B = K). */
+static void cell_fields(const orc_t* o, long x, double* E, double* B)
+{
+    int D = o->D;
+    double rho[9], K[3], Lam[9];
+    moments(D, o->c, &o->g[GI(o, x, 0, 0, 0)], rho, K);
+    for (int k = 0; k < D * D; ++k) Lam[k] = o->cL2[x] * rho[k];
+    efield(D, Lam, E);
+    B[0] = B[1] = B[2] = 0.0;
+    for (int b = 0; b < D; ++b) B[b] = K[b];
+}
+
+int orc_step(orc_t* o, long nsteps, const double* amp)
+{
+    if (!o->have_medium || !o->have_fields) return ORC_ESTATE;
+    int D = o->D, Q = o->Q;
+    long n = o->n;
+    for (long s = 0; s < nsteps; ++s) {
+        double a = amp ? amp[s] : 0.0;
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < n; ++x) {
+            double E[3], B[3], S[3], out[63];
+            cell_fields(o, x, E, B);
+            double cM2 = o->cL2[x] / (double)(D - 1);
+            for (int gm = 0; gm < 3; ++gm) {
+                double mu_term = 0.0;
+                if (o->has_mu)
+                    for (int b = 0; b < 3; ++b)
+                        for (int k = 0; k < 3; ++k)
+                            mu_term += levi(gm, b, k) * B[b] * o->dlnmu[k * n + x];
+                S[gm] = cM2 * mu_term - a * o->jd[gm * n + x] / o->eps_abs[x];
+            }
+            collide_cell(D, o->c, o->w0[x], o->cL2[x], o->tau, &o->g[GI(o, x, 0, 0, 0)], S, out);
+            /* streaming, eq. STREAM: g(x + c_i, t+1) = g'(x, t) */
+            for (int i = 0; i < Q; ++i) {
+                long xd = neighbour(o, x, o->c[i], +1);
+                for (int k = 0; k < D * D; ++k) o->gs[GI(o, xd, i, 0, 0) + k] = out[i * D * D + k];
+            }
+        }
+        double* tmp = o->g; o->g = o->gs; o->gs = tmp;
+        o->t += 1;
+    }
+    return ORC_OK;
+}
+
+/* E, B at the current time, component-major [3][n]. */
+int orc_fields(const orc_t* o, double* E, double* B)
+{
+    if (!o->have_fields) return ORC_ESTATE;
+    long n = o->n;
+    for (long x = 0; x < n; ++x) {
+        double e[3], b[3];
+        cell_fields(o, x, e, b);
+        for (int k = 0; k < 3; ++k) { E[k * n + x] = e[k]; B[k * n + x] = b[k]; }
+    }
+    return ORC_OK;
+}
+
+/* Diagnostics, sequential FP64 sums in cell order:
+ *  out[0] EM energy sum(eps_abs |E|^2 + |B|^2/mu_r)  (energy of the
+ *         heterogeneous-media subsection, with c the Maxwell speed)
+ *  out[1] Q_c = sum_x c_L^2 sum_i sum_{a<b} g_iab^2 / w_i (rest skipped if w0=0)
+ *  out[2] sum (div_h B)^2, central differences
+ *  out[3] sum |B|^2 */
+int orc_diag(const orc_t* o, double* out)
+{
+    if (!o->have_fields) return ORC_ESTATE;
+    int D = o->D, Q = o->Q;
+    long n = o->n;
+    double* Bf = (double*)malloc(sizeof(double) * 3 * n);
+    if (!Bf) return ORC_ENOMEM;
+    double en = 0.0, qc = 0.0, dv = 0.0, bb = 0.0;
+    for (long x = 0; x < n; ++x) {
+        double e[3], b[3];
+        cell_fields(o, x, e, b);
+        for (int k = 0; k < 3; ++k) Bf[k * n + x] = b[k];
+        double e2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+        double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        en += o->eps_abs[x] * e2 + b2 / o->mu_r[x];
+        bb += b2;
+        double q = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            double w = weight(i, o->w0[x], D);
+            if (w == 0.0) continue;
+            double s = 0.0;
+            for (int a = 0; a < D; ++a)
+                for (int bq = a + 1; bq < D; ++bq) {
+                    double v = o->g[GI(o, x, i, a, bq)];
+                    s += v * v;
+                }
+            q += s / w;
+        }
+        qc += o->cL2[x] * q;
+    }
+    for (long x = 0; x < n; ++x) {
+        double d = 0.0;
+        for (int k = 0; k < D; ++k) {
+            int dd[3] = {0, 0, 0};
+            dd[k] = 1;
+            d += 0.5 * (Bf[k * n + neighbour(o, x, dd, +1)] - Bf[k * n + neighbour(o, x, dd, -1)]);
+        }
+        dv += d * d;
+    }
+    free(Bf);
+    out[0] = en; out[1] = qc; out[2] = dv; out[3] = bb;
+    return ORC_OK;
+}
+
+long orc_time(const orc_t* o) { return o->t; }
+long orc_state_size(const orc_t* o) { return o->n * o->Q * o->D * o->D; }
+
+int orc_get_state(const orc_t* o, double* out)
+{
+    memcpy(out, o->g, sizeof(double) * (size_t)orc_state_size(o));
+    return ORC_OK;
+}
+
+int orc_set_state(orc_t* o, const double* in)
+{
+    memcpy(o->g, in, sizeof(double) * (size_t)orc_state_size(o));
+    o->have_fields = 1;
+    return ORC_OK;
+}
+
+/* Medium as prepared (for tests): c_L^2, w0, eps_abs, mu_r, dlnmu[3][n]. */
+int orc_get_medium(const orc_t* o, double* cl2, double* w0, double* eps_abs, double* dlnmu)
+{
+    memcpy(cl2, o->cL2, sizeof(double) * o->n);
+    memcpy(w0, o->w0, sizeof(double) * o->n);
+    memcpy(eps_abs, o->eps_abs, sizeof(double) * o->n);
+    memcpy(dlnmu, o->dlnmu, sizeof(double) * 3 * o->n);
+    return ORC_OK;
+}
+
+/* Stand-alone single-cell pieces for the identity tests. */
+int orc_equilibrium(int D, double w0, const double* Lam, const double* Bbar, double* out)
+{
+    int c[7][3];
+    if (D != 2 && D != 3) return ORC_EINVAL;
+    velocities(D, c);
+    equilibrium(D, c, w0, (1.0 - w0) / D, Lam, Bbar, out);
+    return ORC_OK;
+}
+
+int orc_collide(int D, double w0, double tau, const double* g, const double* S, double* out)
+{
+    int c[7][3];
+    if (D != 2 && D != 3) return ORC_EINVAL;
+    velocities(D, c);
+    collide_cell(D, c, w0, (1.0 - w0) / D, tau, g, S, out);
+    return ORC_OK;
+}
+
+int orc_velocities(int D, int* out)
+{
+    int c[7][3];
+    if (D != 2 && D != 3) return ORC_EINVAL;
+    velocities(D, c);
+    for (int i = 0; i < 2 * D + 1; ++i)
+        for (int a = 0; a < 3; ++a) out[i * 3 + a] = c[i][a];
+    return ORC_OK;
+}
