@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice-BGK Maxwell hot path on one MI355X.
+
+A step is one time step of the whole hot path (gather/stream, moments,
+equilibrium, source, BGK collision, store) over the full lattice.  The primary
+workload is the 2D heterogeneous configuration: 2048^2 periodic lattice, FP32,
+eps = 1 + 3 s(x) (smoothed seeded noise), plane-wave line current with a
+Ricker wavelet.  Inputs are synthetic and resident in HBM before timing.
+
+Prints ONE JSON line.  `value` is MLUPS (million lattice-cell updates per
+second); `roofline` prices the stream-collide kernel against the 8 TB/s HBM
+peak with its algorithmic bytes; `cpu_baseline` is the FP64 CPU oracle on a
+bounded sample of the same workload; `variants` holds the other formats and
+sizes (3D FP32 vs 16-bit deviation storage, HBM-resident sweep points).
+
+Extra modes used for profiling:
+  --only NAME       run one workload (for rocprofv3 runs), no baseline
+  --copy-calibration  a plain device copy of known size (counter calibration)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_per_cell(dim: int, prec: str) -> int:
+    """Algorithmic HBM bytes per lattice update: every stored value read once
+    and written once, plus the c_L^2 medium read."""
+    Q, P = 2 * dim + 1, dim * (dim - 1) // 2
+    if prec == "f64":
+        return 2 * Q * P * 8 + 8
+    if prec == "f32":
+        return 2 * Q * P * 4 + 4
+    return 2 * ((P + dim) * 4 + Q * P * 2) + 4
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_1108_2651_amd/csrc/kernels.h", "paper_1108_2651_amd/csrc/lattice.h",
+              "paper_1108_2651_amd/csrc/lbem.hip"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+_CACHE = {}
+
+
+def make_problem(name: str, nsteps: int):
+    key = (name, nsteps)
+    if key not in _CACHE:
+        _CACHE.clear()
+        _CACHE[key] = _make_problem(name, nsteps)
+    return _CACHE[key]
+
+
+def _make_problem(name: str, nsteps: int):
+    from paper_1108_2651_amd import inputs as I
+    if name == "c2":
+        return I.config2(nsteps=nsteps)
+    if name == "c1":
+        return I.config1(nsteps=nsteps)
+    if name.startswith("2d"):          # "2d8192": the config2 medium tiled periodically
+        n = int(name[2:])
+        p = I.config2(nsteps=nsteps)
+        k = n // 2048
+        eps = np.tile(p.eps_r.reshape(2048, 2048), (k, k)).ravel()
+        cells, w = I.line_source(n, n, 64)
+        return I.Problem(dim=2, shape=(n, n, 1), eps_r=eps, mu_r=None, E0=np.zeros((3, n * n)),
+                         B0=np.zeros((3, n * n)), src_comp=2, src_cells=cells, src_weights=w,
+                         amp=p.amp, nsteps=nsteps, name=f"2d-hetero-{n}")
+    if name == "c3":
+        return I.config3(nsteps=nsteps)
+    if name == "c4":
+        return I.config4(nsteps=nsteps)
+    if name.startswith("3d"):          # "3d128": spheres recipe at another size
+        return I.config3(nsteps=nsteps, n=int(name[2:]))
+    raise ValueError(name)
+
+
+def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str = "auto", p=None):
+    import torch
+
+    from paper_1108_2651_amd import lbem
+    if p is None:
+        p = make_problem(name, warmup + steps)
+    amp = p.amp
+    if amp is None or len(amp) < warmup + steps:
+        from paper_1108_2651_amd import inputs as I
+        amp = I.ricker(warmup + steps, 1.0 / 80.0)
+    s = lbem.Solver(p.dim, p.shape, prec, tau=p.tau, w0_vac=p.w0_vac, streaming=streaming)
+    s.setup(p)
+    stream = torch.cuda.current_stream()
+    s.step(warmup, amp[:warmup])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps, amp[warmup:warmup + steps])
+    e1.record(stream)
+    e1.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    diag = s.energy(check=False)
+    n = p.n
+    bpc = bytes_per_cell(p.dim, prec)
+    mlups = n * steps / (ms * 1e-3) / 1e6
+    gbs = bpc * n * steps / (ms * 1e-3) / 1e9
+    res = dict(workload=p.name, dim=p.dim, shape=list(p.shape), prec=prec,
+               streaming=streaming if streaming != "auto" else ("aa" if (p.dim == 3 and prec in ("f32", "f64")) else "pull"),
+               steps=steps, warmup=warmup, ms_per_step=ms / steps, mlups=mlups,
+               bytes_per_cell=bpc, algorithmic_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+               avg_launch_us=ms * 1e3 / steps, wall_s=wall, finite=diag["status"] == 0,
+               arena_gb=s.arena_bytes / 1e9)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(p, budget_s: float = 15.0) -> dict:
+    """The FP64 oracle as it stands, all host cores, on the full lattice of the
+    primary workload for as many steps as fit the time budget."""
+    from oracle import oracle as O
+    cores = O.set_threads(os.cpu_count() or 1)
+    o = O.Oracle(p.dim, p.shape, p.tau, p.w0_vac)
+    o.set_medium(p.eps_r, p.mu_r)
+    o.init_fields(p.E0, p.B0)
+    o.set_source(p.src_comp, p.src_cells, p.src_weights)
+    t = time.perf_counter()
+    o.step(2, p.amp[:2])
+    per = (time.perf_counter() - t) / 2
+    k = max(1, min(len(p.amp) - 2, int(budget_s / max(per, 1e-9))))
+    t = time.perf_counter()
+    o.step(k, p.amp[2:2 + k])
+    el = time.perf_counter() - t
+    return dict(value=p.n * k / el / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{p.name} full {p.shape[0]}x{p.shape[1]} lattice, FP64 full-tensor oracle, "
+                       f"{k} steps ({el:.1f} s) after 2 untimed",
+                seconds=el)
+
+
+def load_traffic(name: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def copy_calibration(gib: float = 1.0, reps: int = 8):
+    import torch
+    n = int(gib * (1 << 30))
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default=None, help="workload:prec[:streaming], e.g. c2:f32 or c3:f16dev")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU slab decomposition is a design note, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    if args.only:
+        parts = args.only.split(":")
+        r = run_workload(parts[0], parts[1], args.steps, args.warmup,
+                         parts[2] if len(parts) > 2 else "auto")
+        print(json.dumps(r), flush=True)
+        return
+
+    print("[bench] primary: config2 2048^2 FP32", file=sys.stderr, flush=True)
+    p = make_problem("c2", args.warmup + args.steps)
+    prim = run_workload("c2", "f32", args.steps, args.warmup, p=p)
+
+    variants = []
+    if not args.no_variants:
+        plan = [("c2", "f32", "aa", 2000, 20), ("2d8192", "f32", "pull", 200, 10),
+                ("2d8192", "f32", "aa", 200, 10), ("2d8192", "f16dev", "pull", 200, 10),
+                ("c3", "f32", "aa", 200, 10), ("c3", "f32", "pull", 200, 10),
+                ("c3", "f16dev", "pull", 200, 10), ("c3", "bf16dev", "pull", 200, 10),
+                ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5)]
+        plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
+        for name, prec, st, k, w in plan:
+            print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)
+            try:
+                variants.append(run_workload(name, prec, k, w, st, p=make_problem(name, 1100)))
+            except Exception as e:  # report, do not hide
+                variants.append(dict(workload=name, prec=prec, streaming=st, error=str(e)))
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p)
+
+    achieved = prim["bytes_per_cell"] * p.n / (prim["avg_launch_us"] * 1e-6) / 1e9
+    out = {
+        "metric": "MLUPS",
+        "value": prim["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": prim["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D heterogeneous medium eps=1+3s (smoothed seeded noise), 2048x2048 periodic, "
+                               "plane-wave line current j_z at x=64 with Ricker wavelet, FP32, pull streaming",
+                   "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("c2_2048_f32"),
+                     "kernel": "k_step_plain<2,float,R_PULL,W_LOCAL,4,false>",
+                     "bytes_per_cell": prim["bytes_per_cell"], "cells_per_launch": p.n,
+                     "note": "2048^2 FP32 working set (~185 MB) fits the 256 MB Infinity Cache"},
+        "cpu_baseline": cpu,
+        "hbm_frac": prim["hbm_frac"],
+        "finite": prim["finite"],
+        "kernel_source_hash": kernel_source_hash(),
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

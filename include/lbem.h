@@ -1,0 +1,147 @@
+/*
+ * lbem.h -- C ABI of liblbem, an MI355X (gfx950) implementation of the
+ * pseudo-vector lattice-BGK scheme for Maxwell's equations in heterogeneous
+ * media (Hanasoge, Succi & Orszag, "Lattice Boltzmann Method for
+ * Electromagnetic Wave Propagation", arXiv:1108.2651).
+ *
+ * The calls follow the paper's statement of the problem: given the medium
+ * (permittivity and permeability, Section "The Maxwell Equations"), initial
+ * E and B, and a current density j(x,t) (the forcing of Subsection
+ * "Homogeneous media"), advance the lattice-BGK equation (eq. LBE: collision
+ * eq. COLLI then streaming eq. STREAM) on a periodic box and report E, B
+ * (moments, eqs. relate.1-2) and the electromagnetic energy (Subsection
+ * "Heterogeneous media").
+ *
+ * Conventions shared by all calls
+ *  - Lattice units: dx = dt = 1.  A box is nx*ny*nz cells, periodic in every
+ *    direction; 2D means nz == 1 and the TM polarisation (E_z, B_x, B_y).
+ *  - Cell index c = x + nx*(y + ny*z).  Vector fields are component-major
+ *    arrays of 3*n doubles: component k of cell c at [k*n + c].
+ *  - Every call returns an lbem_status (0 on success, negative on error);
+ *    nothing throws across the ABI.  A handle must not be used by two host
+ *    threads at once.  Distinct handles are independent.
+ *  - Host input arrays are copied before the call returns; the caller keeps
+ *    ownership.  Device memory is owned by the handle unless the caller passes
+ *    an arena (lbem_config.dev_mem); then the caller frees the arena after
+ *    lbem_destroy.  Small per-handle tables (source lists, reduction
+ *    partials, upload staging) are always allocated by the handle.
+ *  - Asynchrony: lbem_step only enqueues work on the handle's stream.
+ *    lbem_moments and lbem_energy synchronise that stream.
+ */
+#ifndef LBEM_H
+#define LBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbem_s* lbem_t;
+
+typedef enum {
+    LBEM_OK = 0,
+    LBEM_EINVAL = -1,     /* bad argument (null, out of range, wrong shape)      */
+    LBEM_ENOMEM = -2,     /* device allocation failed or arena too small          */
+    LBEM_EUNSTABLE = -3,  /* medium gives a rest weight w0(x) outside [0,1)       */
+    LBEM_ENONFINITE = -4, /* a diagnostic sum is NaN or Inf                       */
+    LBEM_EDEVICE = -5,    /* HIP runtime error (no device, launch failure, ...)   */
+    LBEM_ESTATE = -6      /* call out of order (e.g. step before init_fields)     */
+} lbem_status;
+
+/* Storage / arithmetic formats of the populations. */
+typedef enum {
+    LBEM_F64 = 0,      /* FP64 populations, FP64 medium, FP64 arithmetic          */
+    LBEM_F32 = 1,      /* FP32 populations, FP32 medium, FP32 arithmetic          */
+    LBEM_F16DEV = 2,   /* FP32 conserved moments + FP16 deviations from the local
+                          equilibrium, scaled by a power of two per velocity;
+                          all collision arithmetic in FP32                        */
+    LBEM_BF16DEV = 3   /* as LBEM_F16DEV with BF16 deviations                     */
+} lbem_prec;
+
+/* Streaming pattern (eq. STREAM) of the stored populations. */
+typedef enum {
+    LBEM_STREAM_AUTO = 0, /* AA for F64/F32 in 3D, pull otherwise                 */
+    LBEM_STREAM_PULL = 1, /* two copies; each step gathers from x - c_i           */
+    LBEM_STREAM_AA = 2    /* one copy updated in place, alternating even/odd steps
+                             (F64/F32 only)                                       */
+} lbem_streaming;
+
+typedef struct {
+    int dim;            /* 2 (TM) or 3                                           */
+    int prec;           /* lbem_prec                                             */
+    int64_t nx, ny, nz; /* box; nz must be 1 when dim == 2; nx*ny*nz < 2^31      */
+    double tau;         /* BGK relaxation time; the paper's choice is 0.5        */
+    double w0_vac;      /* rest weight where eps_r*mu_r == 1, in [0,1); 1/3 is the
+                           usual choice.  Sets the lattice light speed:
+                           c_L^2(x) = (1 - w0_vac)/(dim eps_r mu_r)              */
+    int streaming;      /* lbem_streaming                                        */
+    int mu_varies;      /* 1: reserve room for a non-uniform permeability (adds
+                           the B x grad(ln mu) part of the source); 0: mu == 1    */
+    void* stream;       /* hipStream_t to enqueue on; NULL = the null stream     */
+    void* dev_mem;      /* optional caller-owned device arena, 256-byte aligned  */
+    size_t dev_bytes;   /* its size; must be >= lbem_required_bytes(cfg)         */
+} lbem_config;
+
+/* Device bytes the handle needs for cfg (populations, medium, field scratch);
+ * 0 if cfg is invalid. */
+size_t lbem_required_bytes(const lbem_config* cfg);
+
+/* Create a solver.  On success *out is a new handle (state: no medium, no
+ * fields).  Errors: EINVAL (bad cfg), ENOMEM, EDEVICE. */
+int lbem_create(const lbem_config* cfg, lbem_t* out);
+
+/* Destroy a handle (NULL is accepted).  Synchronises its stream first. */
+int lbem_destroy(lbem_t h);
+
+/* Set the medium: relative permittivity eps_r[n] > 0 and, if mu_r != NULL,
+ * relative permeability mu_r[n] > 0 (host arrays).  The light speed enters
+ * through the rest weight w0(x) = 1 - dim*c_L^2(x) (weights of Section
+ * "Lattice BGK formulation"); EUNSTABLE if some w0 falls outside [0,1), i.e.
+ * eps_r*mu_r < 1 - w0_vac.  A non-uniform mu_r needs cfg.mu_varies (else
+ * EINVAL).  Clears the fields: lbem_init_fields must follow. */
+int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r);
+
+/* Set E(0), B(0) (host arrays of 3*n doubles); the populations start at the
+ * local equilibrium (eq. distrib.func) of these fields.  2D accepts only the
+ * TM components: EINVAL if E_x, E_y or B_z is non-zero.  Resets time to 0.
+ * ESTATE before lbem_set_medium. */
+int lbem_init_fields(lbem_t h, const double* E, const double* B);
+
+/* Current-density footprint: j_comp(cells[k], t) = weight[k] * amp[t] for the
+ * m listed cells (host arrays; repeated cells add up).  comp in {0,1,2}; 2D
+ * accepts comp == 2 only.  m == 0 removes the source.  The source enters the
+ * collision as the tensor term T_i = -(w_i/c^2) eps S with S = -j/eps_abs
+ * (eq. LBE), eps_abs = eps_r/c_vac^2.  ESTATE before lbem_set_medium. */
+int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weight, int64_t m);
+
+/* Enqueue nsteps time steps.  amp (host, nsteps doubles, may be NULL = no
+ * source) gives the source amplitude of each step: step k of this call uses
+ * amp[k] at time t0 + k.  ESTATE before lbem_init_fields. */
+int lbem_step(lbem_t h, int64_t nsteps, const double* amp);
+
+/* E and B at the current time (3*n doubles each, component-major).  With
+ * on_device == 0 they are host pointers, else device pointers on the
+ * handle's device.  Either pointer may be NULL to skip it.  Synchronises. */
+int lbem_moments(lbem_t h, double* E, double* B, int on_device);
+
+/* FP64 diagnostics at the current time (synchronises):
+ *   out[0]  EM energy  sum_x eps_abs |E|^2 + |B|^2/mu_r
+ *   out[1]  Q_c = sum_x c_L^2 sum_i sum_p g_ip^2 / w_i  (exact invariant of
+ *           the scheme at tau = 1/2 with mu == 1 and no source)
+ *   out[2]  sum_x (div_h B)^2, central differences
+ *   out[3]  sum_x |B|^2
+ * ENONFINITE if any of them is NaN or Inf (the values are still written). */
+int lbem_energy(lbem_t h, double out[4]);
+
+/* Completed steps since lbem_init_fields (-1 for an invalid handle). */
+int64_t lbem_time(lbem_t h);
+
+/* Static description of a status code. */
+const char* lbem_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBEM_H */

@@ -1,0 +1,659 @@
+// kernels.h -- gfx950 kernels of the pseudo-vector lattice-BGK Maxwell scheme
+// (Hanasoge, Succi & Orszag, arXiv:1108.2651).
+//
+// One launch = one time step: gather the pre-collision populations (eq.
+// STREAM, applied as a pull or as the in-place AA pattern), form the moments
+// (eqs. relate.1-2 with Bbar = K/(D-1)), the equilibrium (eq. distrib.func),
+// the tensor source T_i = -(w_i/c^2) eps S (eq. LBE), the BGK update
+// (eq. COLLI) and store.  The work is a bandwidth-bound stencil: populations
+// are structure-of-arrays (slot k = i*P + p, then cell), every value is read
+// once and written once per step, no MFMA.
+//
+// Storage formats
+//   plain  : T = double or float per population.
+//   dev    : per cell the post-collision moments (Lambda_p, Bbar_b) in FP32
+//            and, per population, its deviation from the equilibrium of those
+//            moments in FP16/BF16 divided by a power-of-two scale s_i.
+#pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lattice.h"
+
+namespace lbem {
+
+constexpr int NT = 256;  // threads per block (4 wave64)
+
+// read / write patterns of the population slots
+enum { R_LOCAL = 0, R_PULL = 1, R_PULL_SWAP = 2 };
+enum { W_LOCAL = 0, W_SWAP = 1, W_PUSH = 2 };
+
+struct Geo {
+    int nx, ny, nz;
+    int bx_shift;          // block covers BX = 1<<bx_shift cells along x ...
+    int tiles_x, tiles_y;  // ... and RB*VEC rows along y (RB = NT/BX)
+    int nblocks;
+    int xcd;               // remap block ids so each XCD owns a contiguous range
+    int64_t n;
+};
+
+struct Cell {
+    int c;
+    int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Cell make_cell(const Geo& g, int x, int y, int z)
+{
+    Cell C;
+    const int row = g.nx * (y + g.ny * z);
+    C.c = row + x;
+    C.xm = row + (x == 0 ? g.nx - 1 : x - 1);
+    C.xp = row + (x == g.nx - 1 ? 0 : x + 1);
+    const int sy = g.nx;
+    C.ym = C.c + (y == 0 ? (g.ny - 1) * sy : -sy);
+    C.yp = C.c + (y == g.ny - 1 ? -(g.ny - 1) * sy : sy);
+    const int sz = g.nx * g.ny;
+    C.zm = C.c + (z == 0 ? (g.nz - 1) * sz : -sz);
+    C.zp = C.c + (z == g.nz - 1 ? -(g.nz - 1) * sz : sz);
+    return C;
+}
+
+// index of the cell at x + sgn*c_i
+template <int D>
+__device__ __forceinline__ int shifted(const Cell& C, int i, int sgn)
+{
+    if (i == 0) return C.c;
+    const int a = vaxis(D, i), s = vsign(D, i) * sgn;
+    if (a == 0) return s > 0 ? C.xp : C.xm;
+    if (a == 1) return s > 0 ? C.yp : C.ym;
+    return s > 0 ? C.zp : C.zm;
+}
+
+template <int D, int RM>
+__device__ __forceinline__ int read_cell(const Cell& C, int i)
+{
+    return RM == R_LOCAL ? C.c : shifted<D>(C, i, -1);
+}
+template <int D, int RM>
+__device__ __forceinline__ int read_slot(int i)
+{
+    return RM == R_PULL_SWAP ? opp(D, i) : i;
+}
+template <int D, int WM>
+__device__ __forceinline__ int write_cell(const Cell& C, int i)
+{
+    return WM == W_PUSH ? shifted<D>(C, i, +1) : C.c;
+}
+template <int D, int WM>
+__device__ __forceinline__ int write_slot(int i)
+{
+    return WM == W_SWAP ? opp(D, i) : i;
+}
+
+__device__ __forceinline__ int remap_block(int bid, int nb, int on)
+{
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+    // contiguous range of tiles so that neighbouring rows share its L2.
+    if (on && (nb & 7) == 0) return (bid & 7) * (nb >> 3) + (bid >> 3);
+    return bid;
+}
+
+// ---------------------------------------------------------------------------
+// moments and equilibrium pieces shared by all formats
+// ---------------------------------------------------------------------------
+
+// rho_p = sum_i h_ip and K_b = sum_a sum_i c_ia g_iab (pair form)
+template <int D, typename T>
+__device__ __forceinline__ void moments(const T (&f)[Lat<D>::Q][Lat<D>::P], T (&rho)[Lat<D>::P],
+                                        T (&K)[D])
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        T s = f[0][p];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) s += f[i][p];
+        rho[p] = s;
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) K[b] = T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int a = pair_a(D, p), b = pair_b(D, p);
+        // first moments of h_p along a and b
+        const T Ja = f[1 + a][p] - f[1 + D + a][p];
+        const T Jb = f[1 + b][p] - f[1 + D + b][p];
+        K[b] += Ja;
+        K[a] -= Jb;
+    }
+}
+
+// 2*g0 of a moving population: Lambda_p + c_ia Bbar_b - c_ib Bbar_a
+template <int D, typename T>
+__device__ __forceinline__ T twice_eq_moving(int i, int p, T Lam, const T (&Bb)[D])
+{
+    const int a = pair_a(D, p), b = pair_b(D, p);
+    const int ca = cvel(D, i, a), cb = cvel(D, i, b);
+    T A = Lam;
+    if (ca > 0) A += Bb[b];
+    if (ca < 0) A -= Bb[b];
+    if (cb > 0) A -= Bb[a];
+    if (cb < 0) A += Bb[a];
+    return A;
+}
+
+// Source S_gamma = c_M^2 (B x grad ln mu)_gamma (+ sparse current part already
+// in Sp), mapped to pairs: Sp[p] = sgn(p) S_gamma(p).
+template <int D, typename T>
+__device__ __forceinline__ void add_mu_source(const T (&K)[D], T cl2, const T* dl, T (&Sp)[Lat<D>::P])
+{
+    const T cM2 = D == 2 ? cl2 : T(0.5) * cl2;
+    T B[3] = {K[0], K[1], D == 3 ? K[D - 1] : T(0)};
+    T G[3] = {dl[0], dl[1], D == 3 ? dl[2] : T(0)};
+    T S[3];
+    S[0] = cM2 * (B[1] * G[2] - B[2] * G[1]);
+    S[1] = cM2 * (B[2] * G[0] - B[0] * G[2]);
+    S[2] = cM2 * (B[0] * G[1] - B[1] * G[0]);
+#pragma unroll
+    for (int p = 0; p < Lat<D>::P; ++p) Sp[p] += pair_s(D, p) > 0 ? S[pair_g(D, p)] : -S[pair_g(D, p)];
+}
+
+// BGK collision with tensor source, all in precision T.
+// f: pre-collision populations; Sp: source per pair (sgn(p) S_gamma(p));
+// out: post-collision populations.
+template <int D, typename T>
+__device__ __forceinline__ void collide(const T (&f)[Lat<D>::Q][Lat<D>::P], T cl2, const T (&Sp)[Lat<D>::P],
+                                        bool any_src, T omega, bool tau_half,
+                                        const T (&rho)[Lat<D>::P], const T (&K)[D],
+                                        T (&out)[Lat<D>::Q][Lat<D>::P])
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    T Lam[P], Bb[D];
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lam[p] = cl2 * rho[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bb[b] = D == 2 ? K[b] : T(0.5) * K[b];
+    const T w0 = T(1) - T(D) * cl2;
+    const T wc0 = any_src ? (T(1) / cl2 - T(D)) : T(0);  // w0/c^2 of the rest particle
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const T geq = w0 * rho[p];
+        T o = tau_half ? (geq + geq) - f[0][p] : f[0][p] + omega * (geq - f[0][p]);
+        if (any_src) o -= wc0 * Sp[p];
+        out[0][p] = o;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const T A = twice_eq_moving<D, T>(i, p, Lam[p], Bb);
+            T o = tau_half ? A - f[i][p] : f[i][p] + omega * (T(0.5) * A - f[i][p]);
+            if (any_src) o -= T(0.5) * Sp[p];
+            out[i][p] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block decomposition shared by the step kernels
+// ---------------------------------------------------------------------------
+struct Tile {
+    int b;       // logical tile id
+    int x, y0, z;
+    int rb;      // rows per sub-block
+};
+
+__device__ __forceinline__ Tile tile_of(const Geo& g, int vec)
+{
+    Tile t;
+    t.b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tx = t.b % g.tiles_x;
+    const int r = t.b / g.tiles_x;
+    const int ty = r % g.tiles_y;
+    t.z = r / g.tiles_y;
+    const int bx = 1 << g.bx_shift;
+    t.rb = NT >> g.bx_shift;
+    t.x = tx * bx + (threadIdx.x & (bx - 1));
+    t.y0 = ty * t.rb * vec + (threadIdx.x >> g.bx_shift);
+    return t;
+}
+
+// Sparse current source: per tile a range [off[b], off[b+1]) of entries
+// (local cell slot v*NT + tid, pair p) with value sval (S per unit amplitude
+// for that pair).  Staged into LDS by the tiles that own source cells.
+template <typename T>
+struct SrcArgs {
+    const int* off;      // nblocks+1 or nullptr
+    const int2* ent;
+    const T* val;
+    T amp;
+};
+
+template <int P, int VEC, typename T>
+__device__ __forceinline__ bool stage_source(const SrcArgs<T>& s, int b, T* lds)
+{
+    if (s.off == nullptr) return false;
+    const int s0 = s.off[b], s1 = s.off[b + 1];
+    if (s1 <= s0) return false;
+    for (int k = threadIdx.x; k < P * NT * VEC; k += NT) lds[k] = T(0);
+    __syncthreads();
+    for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+        const int2 e = s.ent[k];
+        lds[e.y * NT * VEC + e.x] = s.val[k] * s.amp;
+    }
+    __syncthreads();
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// plain FP64/FP32 stream-collide
+// ---------------------------------------------------------------------------
+template <int D, typename T, int RM, int WM, int VEC, bool MU>
+__global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T* __restrict__ cl2a,
+                                                  const T* __restrict__ dlnmu, const Geo g,
+                                                  const SrcArgs<T> s, const T omega, const int tau_half)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    __shared__ T lds[P * NT * VEC];
+    const Tile t = tile_of(g, VEC);
+    const bool has_src = stage_source<P, VEC, T>(s, t.b, lds);
+    const bool any_src = has_src || MU;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const int y = t.y0 + v * t.rb;
+        if (t.x >= g.nx || y >= g.ny) continue;
+        const Cell C = make_cell(g, t.x, y, t.z);
+        T f[Q][P];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+        const T cl2 = cl2a[C.c];
+        T rho[P], K[D], Sp[P];
+        moments<D, T>(f, rho, K);
+#pragma unroll
+        for (int p = 0; p < P; ++p) Sp[p] = has_src ? lds[p * NT * VEC + v * NT + threadIdx.x] : T(0);
+        if (MU) {
+            T dl[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
+            add_mu_source<D, T>(K, cl2, dl, Sp);
+        }
+        T out[Q][P];
+        collide<D, T>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = out[i][p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deviation storage: FP32 moments + 16-bit scaled deviations, FP32 arithmetic
+// ---------------------------------------------------------------------------
+template <typename H>
+__device__ __forceinline__ float h2f(H v);
+template <>
+__device__ __forceinline__ float h2f<__half>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ float h2f<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+template <typename H>
+__device__ __forceinline__ H f2h(float v);
+template <>
+__device__ __forceinline__ __half f2h<__half>(float v) { return __float2half_rn(v); }
+template <>
+__device__ __forceinline__ __hip_bfloat16 f2h<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+
+// Power-of-two scale per velocity: a moving population's deviation d_i is
+// stored as d_i / s_i; the rest population's as d_0 / (s_0 w0/c^2(x)), which
+// follows its local magnitude (g0_0 = (w0/c^2) Lambda) across the medium.
+struct DevScale {
+    float s[7];
+    float inv[7];
+};
+
+// equilibrium of the stored moments, as used by both the writer and readers
+template <int D>
+__device__ __forceinline__ float dev_eq(int i, int p, const float (&Lam)[Lat<D>::P], const float (&Bb)[D], float wc0)
+{
+    if (i == 0) return wc0 * Lam[p];
+    return 0.5f * twice_eq_moving<D, float>(i, p, Lam[p], Bb);
+}
+
+// Reconstruct population (i,p) stored at cell cs (moments M, deviations Dv).
+template <int D, typename H>
+__device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n, int i, int p, int cs,
+                                          float wc0_here, const DevScale& sc)
+{
+    constexpr int P = Lat<D>::P;
+    float Lam[P], Bb[D];
+    // only the moments this population needs are read (the rest fold away)
+#pragma unroll
+    for (int q = 0; q < P; ++q) Lam[q] = (q == p) ? M[(int64_t)q * n + cs] : 0.f;
+    const int a = pair_a(D, p), b = pair_b(D, p);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        const bool need = i != 0 && ((e == b && cvel(D, i, a) != 0) || (e == a && cvel(D, i, b) != 0));
+        Bb[e] = need ? M[(int64_t)(P + e) * n + cs] : 0.f;
+    }
+    const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0_here);
+    const float si = i == 0 ? sc.s[0] * wc0_here : sc.s[i];
+    return g0 + si * h2f<H>(Dv[(int64_t)(i * P + p) * n + cs]);
+}
+
+template <int D, typename H, int RM, int VEC, bool MU>
+__global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
+                                                const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                                const Geo g, const SrcArgs<float> s, const float omega,
+                                                const int tau_half, const DevScale sc)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    __shared__ float lds[P * NT * VEC];
+    const Tile t = tile_of(g, VEC);
+    const bool has_src = stage_source<P, VEC, float>(s, t.b, lds);
+    const bool any_src = has_src || MU;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const int y = t.y0 + v * t.rb;
+        if (t.x >= g.nx || y >= g.ny) continue;
+        const Cell C = make_cell(g, t.x, y, t.z);
+        const float cl2 = cl2a[C.c];
+        const float wc0 = 1.f / cl2 - float(D);
+        float f[Q][P];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0, sc);
+        float rho[P], K[D], Sp[P];
+        moments<D, float>(f, rho, K);
+#pragma unroll
+        for (int p = 0; p < P; ++p) Sp[p] = has_src ? lds[p * NT * VEC + v * NT + threadIdx.x] : 0.f;
+        if (MU) {
+            float dl[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
+            add_mu_source<D, float>(K, cl2, dl, Sp);
+        }
+        float out[Q][P];
+        collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        // encode: moments of the post-collision state, then deviations
+        float rho2[P], K2[D], Lam2[P], Bb2[D];
+        moments<D, float>(out, rho2, K2);
+#pragma unroll
+        for (int p = 0; p < P; ++p) Lam2[p] = cl2 * rho2[p];
+#pragma unroll
+        for (int b = 0; b < D; ++b) Bb2[b] = D == 2 ? K2[b] : 0.5f * K2[b];
+#pragma unroll
+        for (int p = 0; p < P; ++p) Mout[(int64_t)p * g.n + C.c] = Lam2[p];
+#pragma unroll
+        for (int b = 0; b < D; ++b) Mout[(int64_t)(P + b) * g.n + C.c] = Bb2[b];
+        const float inv0 = sc.inv[0] / wc0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
+                Dout[(int64_t)(i * P + p) * g.n + C.c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// readers for the field / diagnostic kernels
+// ---------------------------------------------------------------------------
+template <int D, typename T, int RM>
+struct PlainReader {
+    const T* pop;
+    int64_t n;
+    __device__ __forceinline__ double get(const Cell& C, int i, int p, double) const
+    {
+        return (double)pop[(int64_t)(read_slot<D, RM>(i) * Lat<D>::P + p) * n + read_cell<D, RM>(C, i)];
+    }
+};
+
+template <int D, typename H, int RM>
+struct DevReader {
+    const float* M;
+    const H* Dv;
+    int64_t n;
+    DevScale sc;
+    __device__ __forceinline__ double get(const Cell& C, int i, int p, double cl2) const
+    {
+        const float wc0 = 1.f / (float)cl2 - float(D);
+        return (double)dev_load<D, H>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0, sc);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// E, B and FP64 diagnostics.  Deterministic two-pass reductions: per-block
+// partials in a fixed tree order, then one block sums the partials.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+struct Geo1 {
+    int nx, ny, nz;
+    int64_t n;
+};
+
+// partials layout: [block][4] = {energy, Q_c, (div B)^2, |B|^2}
+template <int D, typename TM, class R>
+__global__ __launch_bounds__(NT) void k_fields(const R rd, const TM* __restrict__ cl2a,
+                                               const double* __restrict__ mu_r, const Geo1 g1,
+                                               double* E, double* B, double* partials)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    __shared__ double sh[4];
+    const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double en = 0.0, qc = 0.0, b2 = 0.0;
+    if (c64 < g1.n) {
+        const int c = (int)c64;
+        const int x = c % g1.nx, y = (c / g1.nx) % g1.ny, z = c / (g1.nx * g1.ny);
+        Geo g;
+        g.nx = g1.nx; g.ny = g1.ny; g.nz = g1.nz;
+        const Cell C = make_cell(g, x, y, z);
+        const double cl2 = (double)cl2a[c];
+        double f[Q][P];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p) f[i][p] = rd.get(C, i, p, cl2);
+        double rho[P], K[D];
+        moments<D, double>(f, rho, K);
+        double Ev[3] = {0.0, 0.0, 0.0}, Bv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int p = 0; p < P; ++p) Ev[pair_g(D, p)] = -(double)pair_s(D, p) * (cl2 * rho[p]);
+#pragma unroll
+        for (int b = 0; b < D; ++b) Bv[b] = K[b];
+        if (E) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) E[(int64_t)k * g1.n + c] = Ev[k];
+        }
+        if (B) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) B[(int64_t)k * g1.n + c] = Bv[k];
+        }
+        if (partials) {
+            const double mu = mu_r ? mu_r[c] : 1.0;
+            const double eps_abs = (double)(D - 1) / (mu * cl2);
+            const double e2 = Ev[0] * Ev[0] + Ev[1] * Ev[1] + Ev[2] * Ev[2];
+            b2 = Bv[0] * Bv[0] + Bv[1] * Bv[1] + Bv[2] * Bv[2];
+            en = eps_abs * e2 + b2 / mu;
+            const double w0 = 1.0 - (double)D * cl2;
+            double sm = 0.0, s0 = 0.0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) s0 += f[0][p] * f[0][p];
+#pragma unroll
+            for (int i = 1; i < Q; ++i)
+#pragma unroll
+                for (int p = 0; p < P; ++p) sm += f[i][p] * f[i][p];
+            // c_L^2 / w_i = 2 for moving particles; rest skipped when w0 = 0
+            qc = 2.0 * sm + (w0 > 0.0 ? cl2 / w0 * s0 : 0.0);
+        }
+    }
+    if (partials) {
+        const double a = block_sum(en, sh);
+        const double q = block_sum(qc, sh);
+        const double bb = block_sum(b2, sh);
+        if (threadIdx.x == 0) {
+            partials[blockIdx.x * 4 + 0] = a;
+            partials[blockIdx.x * 4 + 1] = q;
+            partials[blockIdx.x * 4 + 3] = bb;
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(NT) void k_divb(const double* __restrict__ B, const Geo1 g1, double* partials)
+{
+    __shared__ double sh[4];
+    const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double dv2 = 0.0;
+    if (c64 < g1.n) {
+        const int c = (int)c64;
+        const int x = c % g1.nx, y = (c / g1.nx) % g1.ny, z = c / (g1.nx * g1.ny);
+        Geo g;
+        g.nx = g1.nx; g.ny = g1.ny; g.nz = g1.nz;
+        const Cell C = make_cell(g, x, y, z);
+        double d = 0.5 * (B[C.xp] - B[C.xm]);
+        d += 0.5 * (B[g1.n + C.yp] - B[g1.n + C.ym]);
+        if (D == 3) d += 0.5 * (B[2 * g1.n + C.zp] - B[2 * g1.n + C.zm]);
+        dv2 = d * d;
+    }
+    const double r = block_sum(dv2, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x * 4 + 2] = r;
+}
+
+__global__ __launch_bounds__(NT) void k_reduce_partials(const double* __restrict__ partials, int nb, double* out)
+{
+    __shared__ double sh[4];
+    for (int k = 0; k < 4; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += NT) s += partials[b * 4 + k];
+        const double r = block_sum(s, sh);
+        if (threadIdx.x == 0) out[k] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels: medium preparation and equilibrium initialisation
+// ---------------------------------------------------------------------------
+
+// c_L^2 = (1 - w0_vac)/(D eps_r mu_r); flag |= 1 when w0 = 1 - D c_L^2 is not
+// in [0,1) or an input is not a positive finite number.
+template <typename TM>
+__global__ __launch_bounds__(NT) void k_medium(const double* __restrict__ eps, const double* __restrict__ mu,
+                                               int D, double w0_vac, const Geo1 g1, TM* cl2, double* mu_out,
+                                               TM* dlnmu, int* flag)
+{
+    const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (c64 >= g1.n) return;
+    const int c = (int)c64;
+    const double e = eps[c], m = mu ? mu[c] : 1.0;
+    bool bad = !(e > 0.0) || !(m > 0.0) || !isfinite(e) || !isfinite(m);
+    const double cl = (1.0 - w0_vac) / ((double)D * e * m);
+    const double w0 = 1.0 - (double)D * cl;
+    bad = bad || !(w0 >= 0.0 && w0 < 1.0);
+    if (bad) atomicOr(flag, 1);
+    cl2[c] = (TM)cl;
+    if (mu_out) {
+        mu_out[c] = m;
+        const int x = c % g1.nx, y = (c / g1.nx) % g1.ny, z = c / (g1.nx * g1.ny);
+        Geo g;
+        g.nx = g1.nx; g.ny = g1.ny; g.nz = g1.nz;
+        const Cell C = make_cell(g, x, y, z);
+        const double mxp = mu ? mu[C.xp] : 1.0, mxm = mu ? mu[C.xm] : 1.0;
+        const double myp = mu ? mu[C.yp] : 1.0, mym = mu ? mu[C.ym] : 1.0;
+        dlnmu[c] = (TM)(0.5 * (log(mxp) - log(mxm)));
+        dlnmu[g1.n + c] = (TM)(0.5 * (log(myp) - log(mym)));
+        if (D == 3) {
+            const double mzp = mu ? mu[C.zp] : 1.0, mzm = mu ? mu[C.zm] : 1.0;
+            dlnmu[2 * g1.n + c] = (TM)(0.5 * (log(mzp) - log(mzm)));
+        }
+    }
+}
+
+// Equilibrium of E0, B0 with Lambda_p = -sgn(p) E_gamma(p), Bbar = B/(D-1),
+// written in the natural (pre-collision, local) layout.
+template <int D>
+__device__ __forceinline__ void init_eq(const double* E, const double* B, int64_t n, int c, double cl2,
+                                        double (&g0)[Lat<D>::Q][Lat<D>::P], double (&Lam)[Lat<D>::P],
+                                        double (&Bb)[D])
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lam[p] = -(double)pair_s(D, p) * E[(int64_t)pair_g(D, p) * n + c];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bb[b] = B[(int64_t)b * n + c] / (double)(D - 1);
+    const double w0 = 1.0 - (double)D * cl2;
+    const double wc = w0 / cl2;
+#pragma unroll
+    for (int p = 0; p < P; ++p) g0[0][p] = wc * Lam[p];
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) g0[i][p] = 0.5 * twice_eq_moving<D, double>(i, p, Lam[p], Bb);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E, const double* __restrict__ B,
+                                                   const T* __restrict__ cl2a, int64_t n, T* pop)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (c64 >= n) return;
+    const int c = (int)c64;
+    double g0[Q][P], Lam[P], Bb[D];
+    init_eq<D>(E, B, n, c, (double)cl2a[c], g0, Lam, Bb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) pop[(int64_t)(i * P + p) * n + c] = (T)g0[i][p];
+}
+
+template <int D, typename H>
+__global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, const double* __restrict__ B,
+                                                 const float* __restrict__ cl2a, int64_t n, float* M, H* Dv,
+                                                 const DevScale sc)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (c64 >= n) return;
+    const int c = (int)c64;
+    const float cl2 = cl2a[c];
+    double g0[Q][P], Lam[P], Bb[D];
+    init_eq<D>(E, B, n, c, (double)cl2, g0, Lam, Bb);
+    float Lf[P], Bf[D];
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lf[p] = (float)Lam[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bf[b] = (float)Bb[b];
+#pragma unroll
+    for (int p = 0; p < P; ++p) M[(int64_t)p * n + c] = Lf[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) M[(int64_t)(P + b) * n + c] = Bf[b];
+    const float wc0 = 1.f / cl2 - float(D);
+    const float inv0 = sc.inv[0] / wc0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float d = (float)(g0[i][p] - (double)dev_eq<D>(i, p, Lf, Bf, wc0));
+            Dv[(int64_t)(i * P + p) * n + c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
+        }
+}
+
+}  // namespace lbem

@@ -1,0 +1,682 @@
+// lbem.hip -- host side of liblbem: handle, device memory, kernel dispatch and
+// the C ABI declared in include/lbem.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbem.h"
+#include "kernels.h"
+
+using namespace lbem;
+
+namespace {
+
+enum Layout { LAYOUT_NATURAL = 0, LAYOUT_PULL_PENDING = 1, LAYOUT_AA_SWAPPED = 2 };
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int env_int(const char* name, int dflt)
+{
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+struct Sizes {
+    size_t pop_one;   // bytes of one copy of the population state
+    size_t copies;
+    size_t medium;    // c_L^2
+    size_t mu;        // mu_r (double) + grad ln mu (medium type) if mu_varies
+    size_t scratch;   // 3*n doubles
+    size_t total;
+};
+
+bool valid_cfg(const lbem_config* c)
+{
+    if (!c) return false;
+    if (c->dim != 2 && c->dim != 3) return false;
+    if (c->prec < LBEM_F64 || c->prec > LBEM_BF16DEV) return false;
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return false;
+    if (c->dim == 2 && c->nz != 1) return false;
+    if (c->nx > (1 << 30) || c->ny > (1 << 30) || c->nz > (1 << 30)) return false;
+    const double n = (double)c->nx * (double)c->ny * (double)c->nz;
+    if (n >= 2147483648.0) return false;
+    if (!(c->tau > 0.0) || !std::isfinite(c->tau)) return false;
+    if (!(c->w0_vac >= 0.0 && c->w0_vac < 1.0)) return false;
+    if (c->streaming < LBEM_STREAM_AUTO || c->streaming > LBEM_STREAM_AA) return false;
+    if (c->streaming == LBEM_STREAM_AA && c->prec >= LBEM_F16DEV) return false;
+    return true;
+}
+
+int resolve_streaming(const lbem_config* c)
+{
+    if (c->streaming != LBEM_STREAM_AUTO) return c->streaming;
+    if (c->prec <= LBEM_F32 && c->dim == 3) return LBEM_STREAM_AA;
+    return LBEM_STREAM_PULL;
+}
+
+Sizes sizes_of(const lbem_config* c)
+{
+    Sizes s{};
+    const int D = c->dim, Q = 2 * D + 1, P = D * (D - 1) / 2;
+    const size_t n = (size_t)(c->nx * c->ny * c->nz);
+    const size_t tm = c->prec == LBEM_F64 ? 8 : 4;
+    if (c->prec <= LBEM_F32)
+        s.pop_one = align256((size_t)Q * P * n * tm);
+    else
+        s.pop_one = align256((size_t)(P + D) * n * 4) + align256((size_t)Q * P * n * 2);
+    s.copies = resolve_streaming(c) == LBEM_STREAM_AA ? 1 : 2;
+    s.medium = align256(n * tm);
+    s.mu = c->mu_varies ? align256(n * 8) + align256((size_t)D * n * tm) : 0;
+    s.scratch = align256(3 * n * 8);
+    s.total = s.pop_one * s.copies + s.medium + s.mu + s.scratch;
+    return s;
+}
+
+}  // namespace
+
+struct Impl;
+
+struct lbem_s {
+    lbem_config cfg;
+    int D, Q, P, prec, streaming;
+    int64_t n;
+    hipStream_t stream;
+    int device;
+    bool own_mem;
+    char* arena;
+    size_t arena_bytes;
+    // population state
+    char* pop[2];
+    int cur;
+    int layout;
+    // medium
+    void* cl2;
+    double* mu_r;
+    void* dlnmu;
+    bool mu_set;
+    // scratch / reductions
+    double* scratch;
+    double* partials;   // nb_diag*4 + 4
+    int nb_diag;
+    // source (device tables, handle-owned)
+    int* src_off;
+    int2* src_ent;
+    void* src_val;
+    int64_t nsrc;
+    // tiling of the step kernels
+    Geo geo;
+    int vec;
+    // deviation scales
+    DevScale sc;
+    double wc0_max;
+    double dev_field_scale;  // field magnitude assumed when E0 = B0 = 0
+    // state
+    int64_t t;
+    bool have_medium, have_fields;
+    Impl* impl;
+};
+
+#define HIP_OK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return LBEM_EDEVICE; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// per (dimension, format) kernel dispatch
+// ---------------------------------------------------------------------------
+struct Impl {
+    virtual ~Impl() {}
+    virtual hipError_t step(lbem_s* h, double amp) = 0;
+    virtual hipError_t fields(lbem_s* h, double* E, double* B, double* partials) = 0;
+    virtual hipError_t init(lbem_s* h, const double* dE, const double* dB) = 0;
+    virtual hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) = 0;
+};
+
+static Geo1 geo1(const lbem_s* h)
+{
+    Geo1 g;
+    g.nx = (int)h->cfg.nx; g.ny = (int)h->cfg.ny; g.nz = (int)h->cfg.nz; g.n = h->n;
+    return g;
+}
+
+static int blocks1(int64_t n) { return (int)((n + NT - 1) / NT); }
+
+template <int D, typename TM>
+static hipError_t launch_medium(lbem_s* h, const double* deps, const double* dmu, int* dflag)
+{
+    hipLaunchKernelGGL((k_medium<TM>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, deps, dmu, D,
+                       h->cfg.w0_vac, geo1(h), (TM*)h->cl2, h->cfg.mu_varies ? h->mu_r : nullptr,
+                       (TM*)h->dlnmu, dflag);
+    return hipGetLastError();
+}
+
+template <int D, typename TM, class R>
+static hipError_t launch_fields(lbem_s* h, const R& rd, double* E, double* B, double* partials)
+{
+    hipLaunchKernelGGL((k_fields<D, TM, R>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, rd,
+                       (const TM*)h->cl2, h->mu_set ? h->mu_r : nullptr, geo1(h), E, B, partials);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+struct PlainImpl : Impl {
+    template <int RM, int WM, int V, bool MU>
+    static hipError_t go(lbem_s* h, const T* src, T* dst, T amp)
+    {
+        SrcArgs<T> s;
+        s.off = h->nsrc ? h->src_off : nullptr;
+        s.ent = h->src_ent;
+        s.val = (const T*)h->src_val;
+        s.amp = amp;
+        const double om = 1.0 / h->cfg.tau;
+        hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
+                           src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
+                           (int)(h->cfg.tau == 0.5));
+        return hipGetLastError();
+    }
+    template <int RM, int WM>
+    static hipError_t go_v(lbem_s* h, const T* src, T* dst, T amp)
+    {
+        if (h->mu_set) return go<RM, WM, 1, true>(h, src, dst, amp);
+        switch (h->vec) {
+            case 2: return go<RM, WM, 2, false>(h, src, dst, amp);
+            case 4:
+                if constexpr (D == 2) return go<RM, WM, 4, false>(h, src, dst, amp);
+                return hipErrorInvalidValue;
+            default: return go<RM, WM, 1, false>(h, src, dst, amp);
+        }
+    }
+    hipError_t step(lbem_s* h, double amp) override
+    {
+        T* a = (T*)h->pop[h->cur];
+        if (h->streaming == LBEM_STREAM_AA) {
+            hipError_t e;
+            if (h->layout == LAYOUT_NATURAL) {
+                e = go_v<R_LOCAL, W_SWAP>(h, a, a, (T)amp);
+                h->layout = LAYOUT_AA_SWAPPED;
+            } else {
+                e = go_v<R_PULL_SWAP, W_PUSH>(h, a, a, (T)amp);
+                h->layout = LAYOUT_NATURAL;
+            }
+            return e;
+        }
+        T* b = (T*)h->pop[1 - h->cur];
+        hipError_t e = h->layout == LAYOUT_NATURAL ? go_v<R_LOCAL, W_LOCAL>(h, a, b, (T)amp)
+                                                   : go_v<R_PULL, W_LOCAL>(h, a, b, (T)amp);
+        h->cur = 1 - h->cur;
+        h->layout = LAYOUT_PULL_PENDING;
+        return e;
+    }
+    hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
+    {
+        const T* a = (const T*)h->pop[h->cur];
+        if (h->layout == LAYOUT_NATURAL) return launch_fields<D, T>(h, PlainReader<D, T, R_LOCAL>{a, h->n}, E, B, partials);
+        if (h->layout == LAYOUT_PULL_PENDING)
+            return launch_fields<D, T>(h, PlainReader<D, T, R_PULL>{a, h->n}, E, B, partials);
+        return launch_fields<D, T>(h, PlainReader<D, T, R_PULL_SWAP>{a, h->n}, E, B, partials);
+    }
+    hipError_t init(lbem_s* h, const double* dE, const double* dB) override
+    {
+        h->cur = 0;
+        h->layout = LAYOUT_NATURAL;
+        hipLaunchKernelGGL((k_init_plain<D, T>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
+                           (const T*)h->cl2, h->n, (T*)h->pop[0]);
+        return hipGetLastError();
+    }
+    hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) override
+    {
+        return launch_medium<D, T>(h, deps, dmu, dflag);
+    }
+};
+
+template <int D, typename H>
+struct DevImpl : Impl {
+    static float* M(lbem_s* h, int k) { return (float*)h->pop[k]; }
+    static H* Dv(lbem_s* h, int k)
+    {
+        const int P = Lat<D>::P;
+        return (H*)(h->pop[k] + align256((size_t)(P + D) * h->n * 4));
+    }
+    template <int RM, int V, bool MU>
+    static hipError_t go(lbem_s* h, int from, int to, float amp)
+    {
+        SrcArgs<float> s;
+        s.off = h->nsrc ? h->src_off : nullptr;
+        s.ent = h->src_ent;
+        s.val = (const float*)h->src_val;
+        s.amp = amp;
+        hipLaunchKernelGGL((k_step_dev<D, H, RM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
+                           M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                           (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
+                           (int)(h->cfg.tau == 0.5), h->sc);
+        return hipGetLastError();
+    }
+    template <int RM>
+    static hipError_t go_v(lbem_s* h, int from, int to, float amp)
+    {
+        if (h->mu_set) return go<RM, 1, true>(h, from, to, amp);
+        switch (h->vec) {
+            case 2: return go<RM, 2, false>(h, from, to, amp);
+            case 4:
+                if constexpr (D == 2) return go<RM, 4, false>(h, from, to, amp);
+                return hipErrorInvalidValue;
+            default: return go<RM, 1, false>(h, from, to, amp);
+        }
+    }
+    hipError_t step(lbem_s* h, double amp) override
+    {
+        hipError_t e = h->layout == LAYOUT_NATURAL ? go_v<R_LOCAL>(h, h->cur, 1 - h->cur, (float)amp)
+                                                   : go_v<R_PULL>(h, h->cur, 1 - h->cur, (float)amp);
+        h->cur = 1 - h->cur;
+        h->layout = LAYOUT_PULL_PENDING;
+        return e;
+    }
+    hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
+    {
+        if (h->layout == LAYOUT_NATURAL)
+            return launch_fields<D, float>(h, DevReader<D, H, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n, h->sc},
+                                           E, B, partials);
+        return launch_fields<D, float>(h, DevReader<D, H, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n, h->sc}, E,
+                                       B, partials);
+    }
+    hipError_t init(lbem_s* h, const double* dE, const double* dB) override
+    {
+        h->cur = 0;
+        h->layout = LAYOUT_NATURAL;
+        hipLaunchKernelGGL((k_init_dev<D, H>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
+                           (const float*)h->cl2, h->n, M(h, 0), Dv(h, 0), h->sc);
+        return hipGetLastError();
+    }
+    hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) override
+    {
+        return launch_medium<D, float>(h, deps, dmu, dflag);
+    }
+};
+
+static Impl* make_impl(int D, int prec)
+{
+    if (D == 2) {
+        switch (prec) {
+            case LBEM_F64: return new (std::nothrow) PlainImpl<2, double>();
+            case LBEM_F32: return new (std::nothrow) PlainImpl<2, float>();
+            case LBEM_F16DEV: return new (std::nothrow) DevImpl<2, __half>();
+            default: return new (std::nothrow) DevImpl<2, __hip_bfloat16>();
+        }
+    }
+    switch (prec) {
+        case LBEM_F64: return new (std::nothrow) PlainImpl<3, double>();
+        case LBEM_F32: return new (std::nothrow) PlainImpl<3, float>();
+        case LBEM_F16DEV: return new (std::nothrow) DevImpl<3, __half>();
+        default: return new (std::nothrow) DevImpl<3, __hip_bfloat16>();
+    }
+}
+
+static void make_geo(lbem_s* h)
+{
+    const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
+    int bx = 64;
+    while (bx < nx && bx < NT) bx <<= 1;
+    int sh = 0;
+    while ((1 << sh) < bx) ++sh;
+    const int rb = NT / bx;
+    Geo& g = h->geo;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
+    g.bx_shift = sh;
+    g.tiles_x = (nx + bx - 1) / bx;
+    g.tiles_y = (ny + rb * h->vec - 1) / (rb * h->vec);
+    g.nblocks = g.tiles_x * g.tiles_y * nz;
+    g.xcd = env_int("LBEM_XCD", 1);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t lbem_required_bytes(const lbem_config* cfg)
+{
+    if (!valid_cfg(cfg)) return 0;
+    return sizes_of(cfg).total;
+}
+
+const char* lbem_strerror(int code)
+{
+    switch (code) {
+        case LBEM_OK: return "success";
+        case LBEM_EINVAL: return "invalid argument";
+        case LBEM_ENOMEM: return "out of device memory or arena too small";
+        case LBEM_EUNSTABLE: return "medium gives a rest weight outside [0,1)";
+        case LBEM_ENONFINITE: return "non-finite diagnostic (NaN or Inf)";
+        case LBEM_EDEVICE: return "HIP device or launch error";
+        case LBEM_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int lbem_create(const lbem_config* cfg, lbem_t* out)
+{
+    if (!out) return LBEM_EINVAL;
+    *out = nullptr;
+    if (!valid_cfg(cfg)) return LBEM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LBEM_EDEVICE;
+    lbem_s* h = new (std::nothrow) lbem_s();
+    if (!h) return LBEM_ENOMEM;
+    std::memset((void*)h, 0, sizeof(*h));
+    h->cfg = *cfg;
+    h->D = cfg->dim;
+    h->Q = 2 * h->D + 1;
+    h->P = h->D * (h->D - 1) / 2;
+    h->prec = cfg->prec;
+    h->streaming = resolve_streaming(cfg);
+    h->n = cfg->nx * cfg->ny * cfg->nz;
+    h->stream = (hipStream_t)cfg->stream;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return LBEM_EDEVICE; }
+    const Sizes s = sizes_of(cfg);
+    if (cfg->dev_mem) {
+        if (cfg->dev_bytes < s.total || ((uintptr_t)cfg->dev_mem & 255)) { delete h; return LBEM_ENOMEM; }
+        h->arena = (char*)cfg->dev_mem;
+        h->own_mem = false;
+    } else {
+        if (hipMalloc((void**)&h->arena, s.total) != hipSuccess) { delete h; return LBEM_ENOMEM; }
+        h->own_mem = true;
+    }
+    h->arena_bytes = s.total;
+    char* p = h->arena;
+    h->pop[0] = p; p += s.pop_one;
+    h->pop[1] = s.copies == 2 ? p : nullptr; p += s.pop_one * (s.copies - 1);
+    h->cl2 = p; p += s.medium;
+    if (cfg->mu_varies) {
+        h->mu_r = (double*)p; p += align256((size_t)h->n * 8);
+        h->dlnmu = p; p += s.mu - align256((size_t)h->n * 8);
+    }
+    h->scratch = (double*)p;
+    h->nb_diag = blocks1(h->n);
+    if (hipMalloc((void**)&h->partials, ((size_t)h->nb_diag * 4 + 4) * sizeof(double)) != hipSuccess) {
+        if (h->own_mem) (void)hipFree(h->arena);
+        delete h;
+        return LBEM_ENOMEM;
+    }
+    int vdef = h->D == 2 ? (h->prec == LBEM_F64 ? 2 : 4) : 1;
+    h->vec = env_int("LBEM_VEC", vdef);
+    if (h->vec != 1 && h->vec != 2 && h->vec != 4) h->vec = vdef;
+    if (h->D == 3 && h->vec == 4) h->vec = 2;
+    if (cfg->mu_varies) h->vec = 1;
+    make_geo(h);
+    for (int i = 0; i < 7; ++i) { h->sc.s[i] = 1.f; h->sc.inv[i] = 1.f; }
+    {
+        const char* v = std::getenv("LBEM_DEV_FIELD_SCALE");
+        h->dev_field_scale = (v && *v) ? std::atof(v) : 1.0;
+        if (!(h->dev_field_scale > 0.0)) h->dev_field_scale = 1.0;
+    }
+    h->impl = make_impl(h->D, h->prec);
+    if (!h->impl) {
+        (void)hipFree(h->partials);
+        if (h->own_mem) (void)hipFree(h->arena);
+        delete h;
+        return LBEM_ENOMEM;
+    }
+    *out = h;
+    return LBEM_OK;
+}
+
+static void free_source(lbem_s* h)
+{
+    if (h->src_off) (void)hipFree(h->src_off);
+    if (h->src_ent) (void)hipFree(h->src_ent);
+    if (h->src_val) (void)hipFree(h->src_val);
+    h->src_off = nullptr; h->src_ent = nullptr; h->src_val = nullptr;
+    h->nsrc = 0;
+}
+
+int lbem_destroy(lbem_t h)
+{
+    if (!h) return LBEM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_source(h);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->own_mem && h->arena) (void)hipFree(h->arena);
+    delete h->impl;
+    delete h;
+    return LBEM_OK;
+}
+
+int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
+{
+    if (!h || !eps_r) return LBEM_EINVAL;
+    const int64_t n = h->n;
+    bool nonunit_mu = false;
+    if (mu_r)
+        for (int64_t c = 0; c < n; ++c)
+            if (mu_r[c] != 1.0) { nonunit_mu = true; break; }
+    if (nonunit_mu && !h->cfg.mu_varies) return LBEM_EINVAL;
+    // largest w0/c_L^2 = D eps mu/(1-w0_vac) - D, for the rest-particle scale
+    double wmax = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+        const double em = eps_r[c] * (mu_r ? mu_r[c] : 1.0);
+        const double v = (double)h->D * em / (1.0 - h->cfg.w0_vac) - (double)h->D;
+        if (std::isfinite(v)) wmax = std::max(wmax, v);
+    }
+    double *deps = nullptr, *dmu = nullptr;
+    int* dflag = nullptr;
+    int flag = 0, rc = LBEM_OK;
+    if (hipMalloc((void**)&deps, n * 8) != hipSuccess) return LBEM_ENOMEM;
+    if (mu_r && hipMalloc((void**)&dmu, n * 8) != hipSuccess) { (void)hipFree(deps); return LBEM_ENOMEM; }
+    if (hipMalloc((void**)&dflag, sizeof(int)) != hipSuccess) {
+        (void)hipFree(deps);
+        if (dmu) (void)hipFree(dmu);
+        return LBEM_ENOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(deps, eps_r, n * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && mu_r) e = hipMemcpyAsync(dmu, mu_r, n * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(dflag, 0, sizeof(int), h->stream);
+    h->mu_set = h->cfg.mu_varies != 0;
+    if (e == hipSuccess) e = h->impl->medium(h, deps, dmu, dflag);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = LBEM_EDEVICE;
+    else if (flag) rc = LBEM_EUNSTABLE;
+    (void)hipFree(deps);
+    if (dmu) (void)hipFree(dmu);
+    (void)hipFree(dflag);
+    h->have_medium = rc == LBEM_OK;
+    h->have_fields = false;
+    h->wc0_max = wmax;
+    return rc;
+}
+
+static float pow2_at_least(double v)
+{
+    if (!(v > 0.0) || !std::isfinite(v)) return 1.f;
+    return (float)std::ldexp(1.0, (int)std::ceil(std::log2(v)));
+}
+
+int lbem_init_fields(lbem_t h, const double* E, const double* B)
+{
+    if (!h || !E || !B) return LBEM_EINVAL;
+    if (!h->have_medium) return LBEM_ESTATE;
+    const int64_t n = h->n;
+    double amax = 0.0;
+    for (int64_t k = 0; k < 3 * n; ++k) {
+        if (!std::isfinite(E[k]) || !std::isfinite(B[k])) return LBEM_EINVAL;
+        amax = std::max(amax, std::max(std::fabs(E[k]), std::fabs(B[k])));
+    }
+    if (h->D == 2) {
+        for (int64_t c = 0; c < n; ++c)
+            if (E[c] != 0.0 || E[n + c] != 0.0 || B[2 * n + c] != 0.0) return LBEM_EINVAL;
+    }
+    // power-of-two scales per velocity: populations are bounded by the field
+    // magnitude times w_i/c^2 (1/2 moving; the rest scale is further
+    // multiplied in the kernels by the local w0/c^2)
+    const double A = amax > 0.0 ? amax : h->dev_field_scale;
+    for (int i = 0; i < 7; ++i) {
+        h->sc.s[i] = pow2_at_least(i == 0 ? A : 0.5 * A);
+        h->sc.inv[i] = 1.f / h->sc.s[i];
+    }
+    double *dE = nullptr, *dB = nullptr;
+    if (hipMalloc((void**)&dE, 3 * n * 8) != hipSuccess) return LBEM_ENOMEM;
+    if (hipMalloc((void**)&dB, 3 * n * 8) != hipSuccess) { (void)hipFree(dE); return LBEM_ENOMEM; }
+    hipError_t e = hipMemcpyAsync(dE, E, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dB, B, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = h->impl->init(h, dE, dB);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(dE);
+    (void)hipFree(dB);
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->t = 0;
+    h->have_fields = true;
+    return LBEM_OK;
+}
+
+int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weight, int64_t m)
+{
+    if (!h || m < 0 || comp < 0 || comp > 2) return LBEM_EINVAL;
+    if (h->D == 2 && comp != 2) return LBEM_EINVAL;
+    if (m > 0 && (!cells || !weight)) return LBEM_EINVAL;
+    if (!h->have_medium) return LBEM_ESTATE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
+    free_source(h);
+    if (m == 0) return LBEM_OK;
+    const int64_t n = h->n;
+    const int D = h->D;
+    // pair carrying component comp and its Levi-Civita sign
+    int pp = -1, sg = 0;
+    for (int p = 0; p < h->P; ++p)
+        if (pair_g(D, p) == comp) { pp = p; sg = pair_s(D, p); }
+    // eps_abs = eps_r/c_vac^2 = (D-1)/(mu_r c_L^2): read back c_L^2 and mu_r
+    std::vector<double> cl2(n), mu(n, 1.0);
+    if (h->prec == LBEM_F64) {
+        if (hipMemcpy(cl2.data(), h->cl2, n * 8, hipMemcpyDeviceToHost) != hipSuccess) return LBEM_EDEVICE;
+    } else {
+        std::vector<float> f(n);
+        if (hipMemcpy(f.data(), h->cl2, n * 4, hipMemcpyDeviceToHost) != hipSuccess) return LBEM_EDEVICE;
+        for (int64_t c = 0; c < n; ++c) cl2[c] = f[c];
+    }
+    if (h->mu_set && hipMemcpy(mu.data(), h->mu_r, n * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return LBEM_EDEVICE;
+    // merge repeated cells, then bucket by tile
+    std::vector<std::pair<int64_t, double>> ent;
+    ent.reserve(m);
+    for (int64_t k = 0; k < m; ++k) {
+        if (cells[k] < 0 || cells[k] >= n || !std::isfinite(weight[k])) return LBEM_EINVAL;
+        ent.push_back({cells[k], weight[k]});
+    }
+    std::sort(ent.begin(), ent.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    std::vector<std::pair<int64_t, double>> merged;
+    for (auto& e : ent) {
+        if (!merged.empty() && merged.back().first == e.first) merged.back().second += e.second;
+        else merged.push_back(e);
+    }
+    const Geo& g = h->geo;
+    const int bx = 1 << g.bx_shift, rb = NT / bx;
+    struct Item { int b; int local; double v; };
+    std::vector<Item> items;
+    items.reserve(merged.size());
+    for (auto& e : merged) {
+        const int c = (int)e.first;
+        const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
+        const int tx = x / bx, ty = y / (rb * h->vec);
+        const int b = (z * g.tiles_y + ty) * g.tiles_x + tx;
+        const int yr = y - ty * rb * h->vec;
+        const int v = yr / rb, tyi = yr % rb;
+        const int local = v * NT + tyi * bx + (x - tx * bx);
+        // S per unit amplitude on pair pp: sgn * (-weight/eps_abs)
+        const double eps_abs = (double)(D - 1) / (mu[c] * cl2[c]);
+        items.push_back({b, local, -(double)sg * e.second / eps_abs});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.b < b.b; });
+    std::vector<int> off(g.nblocks + 1, 0);
+    for (auto& it : items) off[it.b + 1]++;
+    for (int b = 0; b < g.nblocks; ++b) off[b + 1] += off[b];
+    std::vector<int2> ents(items.size());
+    for (size_t k = 0; k < items.size(); ++k) ents[k] = make_int2(items[k].local, pp);
+    const size_t ms = items.size();
+    const size_t tv = h->prec == LBEM_F64 ? 8 : 4;
+    if (hipMalloc((void**)&h->src_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->src_ent, ms * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->src_val, ms * tv) != hipSuccess) {
+        free_source(h);
+        return LBEM_ENOMEM;
+    }
+    hipError_t e = hipMemcpy(h->src_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->src_ent, ents.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        if (tv == 8) {
+            std::vector<double> v(ms);
+            for (size_t k = 0; k < ms; ++k) v[k] = items[k].v;
+            e = hipMemcpy(h->src_val, v.data(), ms * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> v(ms);
+            for (size_t k = 0; k < ms; ++k) v[k] = (float)items[k].v;
+            e = hipMemcpy(h->src_val, v.data(), ms * 4, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) { free_source(h); return LBEM_EDEVICE; }
+    h->nsrc = (int64_t)ms;
+    return LBEM_OK;
+}
+
+int lbem_step(lbem_t h, int64_t nsteps, const double* amp)
+{
+    if (!h || nsteps < 0) return LBEM_EINVAL;
+    if (!h->have_fields) return LBEM_ESTATE;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const double a = (amp && h->nsrc) ? amp[k] : 0.0;
+        if (h->impl->step(h, a) != hipSuccess) return LBEM_EDEVICE;
+        h->t += 1;
+    }
+    return LBEM_OK;
+}
+
+int lbem_moments(lbem_t h, double* E, double* B, int on_device)
+{
+    if (!h) return LBEM_EINVAL;
+    if (!h->have_fields) return LBEM_ESTATE;
+    const size_t bytes = (size_t)3 * h->n * 8;
+    if (on_device) {
+        if (h->impl->fields(h, E, B, nullptr) != hipSuccess) return LBEM_EDEVICE;
+        return hipStreamSynchronize(h->stream) == hipSuccess ? LBEM_OK : LBEM_EDEVICE;
+    }
+    if (E) {
+        HIP_OK(h->impl->fields(h, h->scratch, nullptr, nullptr));
+        HIP_OK(hipMemcpyAsync(E, h->scratch, bytes, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
+    if (B) {
+        HIP_OK(h->impl->fields(h, nullptr, h->scratch, nullptr));
+        HIP_OK(hipMemcpyAsync(B, h->scratch, bytes, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
+    return LBEM_OK;
+}
+
+int lbem_energy(lbem_t h, double out[4])
+{
+    if (!h || !out) return LBEM_EINVAL;
+    if (!h->have_fields) return LBEM_ESTATE;
+    double* res = h->partials + (size_t)h->nb_diag * 4;
+    HIP_OK(h->impl->fields(h, nullptr, h->scratch, h->partials));
+    Geo1 g = geo1(h);
+    if (h->D == 2)
+        hipLaunchKernelGGL((k_divb<2>), dim3(h->nb_diag), dim3(NT), 0, h->stream, h->scratch, g, h->partials);
+    else
+        hipLaunchKernelGGL((k_divb<3>), dim3(h->nb_diag), dim3(NT), 0, h->stream, h->scratch, g, h->partials);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(NT), 0, h->stream, h->partials, h->nb_diag, res);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(out[k])) return LBEM_ENONFINITE;
+    return LBEM_OK;
+}
+
+int64_t lbem_time(lbem_t h) { return h ? h->t : -1; }
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances: relative L2 of E and of B <= 1e-12 for the
+FP64 format and <= 1e-5 for FP32 after up to 1000 steps; the deviation
+formats against the FP64 oracle at 1e-3 (FP16) and 1e-2 (BF16)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, gpu_run, oracle_run, random_problem, rel
+from paper_1108_2651_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "bf16dev": 1e-2}
+
+
+def compare(p, nsteps, prec, streaming="auto", tau=None, env=None, tol=None):
+    announce(f"{p.name} {p.shape} prec={prec} streaming={streaming} steps={nsteps} env={env}")
+    s = gpu_run(p, nsteps, prec, streaming, tau=tau, env=env)
+    Eg, Bg = s.moments()
+    o = oracle_run(p, nsteps, tau=tau)
+    Eo, Bo = o.fields()
+    eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+    announce(f"  rel L2 E={eE:.3e} B={eB:.3e}")
+    t = TOL[prec] if tol is None else tol
+    assert eE <= t and eB <= t, (eE, eB)
+    assert s.t == nsteps
+    return s, o
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_config1_homogeneous_pulse_1000_steps(prec, streaming):
+    p = inputs.config1()
+    compare(p, 1000, prec, streaming)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config2_recipe_line_source(prec):
+    # the heterogeneous 2D recipe (smoothed eps in [1,4], Ricker line current)
+    # at 192^2: not a multiple of the 256-wide tile, several tiles per row group
+    p = inputs.config2(nsteps=600, n=192)
+    compare(p, 600, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_config3_crop_spheres_dipole(prec, streaming):
+    p = inputs.config3(nsteps=400, crop_n=32)
+    compare(p, 400, prec, streaming)
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (100, 37, 1)), (2, (1, 64, 1)), (2, (300, 2, 1)),
+                                       (3, (5, 3, 7)), (3, (33, 17, 9)), (3, (70, 1, 4))])
+@pytest.mark.parametrize("mu", [False, True])
+def test_ragged_shapes_all_terms(dim, shape, mu):
+    p = random_problem(dim, shape, seed=sum(shape) + 7 * mu, mu=mu, nsteps=61)
+    for streaming in (["pull", "aa"] if not mu else ["pull"]):
+        compare(p, 61, "f64", streaming)
+    compare(p, 61, "f32", "auto", tol=2e-5)
+
+
+def test_tau_not_half():
+    p = random_problem(2, (40, 24, 1), seed=3, nsteps=80)
+    compare(p, 80, "f64", tau=0.8)
+    p3 = random_problem(3, (12, 10, 8), seed=4, nsteps=40)
+    compare(p3, 40, "f64", tau=1.3)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_diagnostics_match_oracle(dim, streaming):
+    shape = (48, 40, 1) if dim == 2 else (20, 16, 12)
+    p = random_problem(dim, shape, seed=60 + dim, src=False)
+    for nsteps in (0, 1, 2, 7):
+        announce(f"diag dim={dim} {streaming} steps={nsteps}")
+        s = gpu_run(p, nsteps, "f64", streaming)
+        o = oracle_run(p, nsteps)
+        dg, do = s.energy(), o.diag()
+        for k in ("energy", "qc", "divb2", "b2"):
+            assert abs(dg[k] - do[k]) <= 1e-12 * abs(do[k]), (k, dg[k], do[k])
+
+
+def test_qc_invariant_f64_gpu():
+    p = random_problem(3, (24, 20, 16), seed=71, src=False)
+    s = gpu_run(p, 0, "f64")
+    q0 = s.energy()["qc"]
+    s.step(1000)
+    assert abs(s.energy()["qc"] / q0 - 1) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_aa_pull_and_tilings_bitwise(dim):
+    """In-place AA streaming, double-buffered pull, different cells-per-thread
+    and block-to-XCD mappings all give bit-identical fields (race check)."""
+    p = random_problem(dim, (96, 40, 1) if dim == 2 else (40, 24, 20), seed=80 + dim, nsteps=77)
+    ref = gpu_run(p, 77, "f32", "pull").moments()
+    variants = [dict(streaming="aa"), dict(streaming="pull", env={"LBEM_XCD": 0}),
+                dict(streaming="aa", env={"LBEM_VEC": 2})]
+    if dim == 2:
+        variants.append(dict(streaming="pull", env={"LBEM_VEC": 1}))
+        variants.append(dict(streaming="aa", env={"LBEM_VEC": 4}))
+    for v in variants:
+        announce(f"bitwise dim={dim} {v}")
+        got = gpu_run(p, 77, "f32", v["streaming"], env=v.get("env")).moments()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), v
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_storage_config1(prec):
+    p = inputs.config1()
+    compare(p, 1000, prec)
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_storage_3d_crop(prec):
+    p = inputs.config3(nsteps=300, crop_n=32)
+    compare(p, 300, prec)
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_storage_ragged_mu(prec):
+    # white-noise fields are far from equilibrium, so the 16-bit deviations
+    # carry O(1) of each population: a code-path check with a looser bound
+    tol = 5e-3 if prec == "f16dev" else 4e-2
+    p = random_problem(3, (19, 13, 11), seed=90, mu=True, nsteps=40)
+    compare(p, 40, prec, tol=tol)
+    p2 = random_problem(2, (77, 29, 1), seed=91, mu=False, nsteps=40)
+    compare(p2, 40, prec, tol=tol)
+
+
+def test_moments_on_device():
+    import torch
+    p = random_problem(3, (16, 12, 10), seed=5, nsteps=9)
+    s = gpu_run(p, 9, "f64")
+    E = torch.empty(3 * p.n, dtype=torch.float64, device="cuda")
+    B = torch.empty(3 * p.n, dtype=torch.float64, device="cuda")
+    s.moments_device(E, B)
+    Eh, Bh = s.moments()
+    assert np.array_equal(E.cpu().numpy(), Eh.ravel()) and np.array_equal(B.cpu().numpy(), Bh.ravel())
