@@ -250,7 +250,7 @@ def main():
                    "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("c2_2048_f32"),
-                     "kernel": "k_step_plain<2,float,R_PULL,W_LOCAL,4,false>",
+                     "kernel": "k_step_plain<2,float,R_PULL,W_LOCAL,1,false>",
                      "bytes_per_cell": prim["bytes_per_cell"], "cells_per_launch": p.n,
                      "note": "2048^2 FP32 working set (~185 MB) fits the 256 MB Infinity Cache"},
         "cpu_baseline": cpu,

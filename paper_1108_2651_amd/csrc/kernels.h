@@ -35,8 +35,25 @@ struct Geo {
     int tiles_x, tiles_y;  // ... and RB*VEC rows along y (RB = NT/BX)
     int nblocks;
     int xcd;               // remap block ids so each XCD owns a contiguous range
+    int strip;             // >0: tiles ordered as strips of `strip` tile-rows
+                           // marching through z (keeps z-neighbours in L2)
     int64_t n;
 };
+
+// logical tile id -> (tile_x, tile_y, z); the host mirrors this in tile_id()
+__host__ __device__ __forceinline__ void tile_coords(const Geo& g, int b, int& tx, int& ty, int& z)
+{
+    tx = b % g.tiles_x;
+    const int r = b / g.tiles_x;
+    if (g.strip > 0) {
+        const int rs = r % g.strip, r2 = r / g.strip;
+        z = r2 % g.nz;
+        ty = (r2 / g.nz) * g.strip + rs;
+    } else {
+        ty = r % g.tiles_y;
+        z = r / g.tiles_y;
+    }
+}
 
 struct Cell {
     int c;
@@ -208,10 +225,8 @@ __device__ __forceinline__ Tile tile_of(const Geo& g, int vec)
 {
     Tile t;
     t.b = remap_block(blockIdx.x, g.nblocks, g.xcd);
-    const int tx = t.b % g.tiles_x;
-    const int r = t.b / g.tiles_x;
-    const int ty = r % g.tiles_y;
-    t.z = r / g.tiles_y;
+    int tx, ty;
+    tile_coords(g, t.b, tx, ty, t.z);
     const int bx = 1 << g.bx_shift;
     t.rb = NT >> g.bx_shift;
     t.x = tx * bx + (threadIdx.x & (bx - 1));

@@ -331,7 +331,20 @@ static void make_geo(lbem_s* h)
     g.tiles_x = (nx + bx - 1) / bx;
     g.tiles_y = (ny + rb * h->vec - 1) / (rb * h->vec);
     g.nblocks = g.tiles_x * g.tiles_y * nz;
-    g.xcd = env_int("LBEM_XCD", 1);
+    // measured defaults: XCD-contiguous tile ranges help 2D, not 3D AA
+    g.xcd = env_int("LBEM_XCD", h->D == 2 ? 1 : 0);
+    const int sdef = (h->D == 3 && h->prec >= LBEM_F16DEV) ? 32 : 0;
+    g.strip = env_int("LBEM_STRIP", sdef);
+    if (g.strip <= 0 || nz == 1 || g.strip >= g.tiles_y || g.tiles_y % g.strip != 0) g.strip = 0;
+}
+
+// inverse of tile_coords()
+static int tile_id(const Geo& g, int tx, int ty, int z)
+{
+    int r;
+    if (g.strip > 0) r = ((ty / g.strip) * g.nz + z) * g.strip + ty % g.strip;
+    else r = z * g.tiles_y + ty;
+    return r * g.tiles_x + tx;
 }
 
 // ---------------------------------------------------------------------------
@@ -403,7 +416,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
         delete h;
         return LBEM_ENOMEM;
     }
-    int vdef = h->D == 2 ? (h->prec == LBEM_F64 ? 2 : 4) : 1;
+    int vdef = 1;
     h->vec = env_int("LBEM_VEC", vdef);
     if (h->vec != 1 && h->vec != 2 && h->vec != 4) h->vec = vdef;
     if (h->D == 3 && h->vec == 4) h->vec = 2;
@@ -582,7 +595,7 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
         const int c = (int)e.first;
         const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
         const int tx = x / bx, ty = y / (rb * h->vec);
-        const int b = (z * g.tiles_y + ty) * g.tiles_x + tx;
+        const int b = tile_id(g, tx, ty, z);
         const int yr = y - ty * rb * h->vec;
         const int v = yr / rb, tyi = yr % rb;
         const int local = v * NT + tyi * bx + (x - tx * bx);

@@ -1,7 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs.  Tolerances: relative L2 of E and of B <= 1e-12 for the
-FP64 format and <= 1e-5 for FP32 after up to 1000 steps; the deviation
-formats against the FP64 oracle at 1e-3 (FP16) and 1e-2 (BF16)."""
+FP64 format and <= 1e-5 for FP32 after up to 1000 steps.  The 16-bit
+deviation formats are judged in the energy norm
+sqrt(sum eps_abs|dE|^2 + |dB|^2/mu) / sqrt(sum eps_abs|E|^2 + |B|^2/mu)
+(<= 1e-3 FP16, <= 1e-2 BF16) with each field's relative L2 reported and held
+to twice that: a field's own norm can pass through a temporal node (E in a
+resonant periodic box), where its relative error is not meaningful."""
 import numpy as np
 import pytest
 
@@ -13,6 +17,14 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "bf16dev": 1e-2}
 
 
+def energy_norm_error(Eg, Bg, Eo, Bo, o, mu=None):
+    ea = o.medium()["eps_abs"]
+    m = 1.0 if mu is None else mu
+    num = np.sum(ea * ((Eg - Eo) ** 2).sum(0) + ((Bg - Bo) ** 2).sum(0) / m)
+    den = np.sum(ea * (Eo ** 2).sum(0) + (Bo ** 2).sum(0) / m)
+    return float(np.sqrt(num / den))
+
+
 def compare(p, nsteps, prec, streaming="auto", tau=None, env=None, tol=None):
     announce(f"{p.name} {p.shape} prec={prec} streaming={streaming} steps={nsteps} env={env}")
     s = gpu_run(p, nsteps, prec, streaming, tau=tau, env=env)
@@ -20,9 +32,13 @@ def compare(p, nsteps, prec, streaming="auto", tau=None, env=None, tol=None):
     o = oracle_run(p, nsteps, tau=tau)
     Eo, Bo = o.fields()
     eE, eB = rel(Eg, Eo), rel(Bg, Bo)
-    announce(f"  rel L2 E={eE:.3e} B={eB:.3e}")
+    eN = energy_norm_error(Eg, Bg, Eo, Bo, o, p.mu_r)
+    announce(f"  rel L2 E={eE:.3e} B={eB:.3e} energy-norm={eN:.3e}")
     t = TOL[prec] if tol is None else tol
-    assert eE <= t and eB <= t, (eE, eB)
+    if prec in ("f64", "f32"):
+        assert eE <= t and eB <= t, (eE, eB)
+    else:
+        assert eN <= t and eE <= 2 * t and eB <= 2 * t, (eN, eE, eB)
     assert s.t == nsteps
     return s, o
 
@@ -96,6 +112,9 @@ def test_aa_pull_and_tilings_bitwise(dim):
     ref = gpu_run(p, 77, "f32", "pull").moments()
     variants = [dict(streaming="aa"), dict(streaming="pull", env={"LBEM_XCD": 0}),
                 dict(streaming="aa", env={"LBEM_VEC": 2})]
+    if dim == 3:
+        variants.append(dict(streaming="pull", env={"LBEM_STRIP": 3}))
+        variants.append(dict(streaming="aa", env={"LBEM_STRIP": 2, "LBEM_XCD": 0}))
     if dim == 2:
         variants.append(dict(streaming="pull", env={"LBEM_VEC": 1}))
         variants.append(dict(streaming="aa", env={"LBEM_VEC": 4}))
@@ -126,6 +145,18 @@ def test_deviation_storage_ragged_mu(prec):
     compare(p, 40, prec, tol=tol)
     p2 = random_problem(2, (77, 29, 1), seed=91, mu=False, nsteps=40)
     compare(p2, 40, prec, tol=tol)
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_tile_orders_bitwise(prec):
+    """Strip / row-major tile orders and XCD remapping of the deviation kernel
+    give identical results, with a source spread over many tiles."""
+    p = random_problem(3, (64, 48, 10), seed=95, nsteps=30)
+    ref = gpu_run(p, 30, prec, env={"LBEM_STRIP": 0}).moments()
+    for env in ({"LBEM_STRIP": 4}, {"LBEM_STRIP": 2, "LBEM_XCD": 0}, {"LBEM_VEC": 2, "LBEM_STRIP": 3}):
+        announce(f"dev tile order {prec} {env}")
+        got = gpu_run(p, 30, prec, env=env).moments()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
 
 
 def test_moments_on_device():
