@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--only", default=None, help="workload:prec[:streaming], e.g. c2:f32 or c3:f16dev")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -226,6 +228,24 @@ def main():
             except Exception as e:  # report, do not hide
                 variants.append(dict(workload=name, prec=prec, streaming=st, error=str(e)))
 
+    serving = None
+    if not args.no_serving:
+        from paper_1108_2651_amd import serve as SV
+        serving = {}
+        for rate in (200.0, 100.0):
+            print(f"[bench] serving mix at {rate:.0f} req/s", file=sys.stderr, flush=True)
+            reqs = SV.make_requests(count=args.serve_requests, rate=rate)
+            rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=50, workers=6)
+            serving[f"{rate:.0f}_req_per_s"] = dict(
+                requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
+                p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
+                mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,
+                mean_resident=rep.mean_resident, max_resident=rep.max_resident,
+                offered_mlups=sum(r.cells * r.nsteps for r in reqs) / reqs[-1].t_arrive / 1e6)
+        serving["config"] = ("Poisson arrivals; 70% 2D 64^2-1024^2, 30% 3D 32^3-128^3; smooth eps in [1,4]; "
+                             "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 50 steps per tick; "
+                             "latency = arrival to E,B on the host")
+
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -258,6 +278,7 @@ def main():
         "finite": prim["finite"],
         "kernel_source_hash": kernel_source_hash(),
         "variants": variants,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

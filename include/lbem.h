@@ -141,6 +141,36 @@ int64_t lbem_time(lbem_t h);
 /* Static description of a status code. */
 const char* lbem_strerror(int code);
 
+/* ---- batched stepping of many resident lattices (continuous-batching serving) ----
+ *
+ * A batch advances several independent handles together: each step of a tick
+ * is one persistent launch per (dim, format) class that strides over all
+ * (lattice, tile) work items of the handles in that class.  A tick is
+ * steps_per_tick such steps, captured once as a HIP graph per set of classes
+ * present and replayed; the per-lattice table it reads is uploaded before each
+ * tick, so lattices can join and leave between ticks.  Results are bit-for-bit
+ * those of lbem_step on each handle alone.
+ */
+typedef struct lbem_batch_s* lbem_batch_t;
+
+/* max_lattices: capacity of one tick (1..65536); steps_per_tick: K (1..4096);
+ * stream: the hipStream_t the ticks run on (not NULL: it is captured).
+ * Member handles may live on other streams: each tick waits for the work
+ * already enqueued on a member's stream, and later work on that stream
+ * (lbem_moments, lbem_destroy) waits for the tick.  Errors: EINVAL, ENOMEM. */
+int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_batch_t* out);
+
+/* Enqueue one tick on the batch stream: handle k advances by nsteps[k] steps
+ * (0 <= nsteps[k] <= steps_per_tick; 0 leaves it untouched).  Members must be
+ * distinct, initialised (ESTATE otherwise), created with pull streaming,
+ * without a current source and with mu == 1 (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member synchronises.
+ * The host-side table is double-buffered: a call waits only for the upload of
+ * the tick before the previous one. */
+int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count);
+
+/* Destroy a batch (NULL accepted); synchronises its stream. */
+int lbem_batch_destroy(lbem_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -359,6 +359,33 @@ __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n
     return g0 + si * h2f<H>(Dv[(int64_t)(i * P + p) * n + cs]);
 }
 
+// Encode a post-collision state: its moments (FP32) and the scaled 16-bit
+// deviations from the equilibrium of those moments.
+template <int D, typename H>
+__device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
+                                          const DevScale& sc, int64_t n, int c, float* Mout, H* Dout)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    float rho2[P], K2[D], Lam2[P], Bb2[D];
+    moments<D, float>(out, rho2, K2);
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lam2[p] = cl2 * rho2[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bb2[b] = D == 2 ? K2[b] : 0.5f * K2[b];
+#pragma unroll
+    for (int p = 0; p < P; ++p) Mout[(int64_t)p * n + c] = Lam2[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Mout[(int64_t)(P + b) * n + c] = Bb2[b];
+    const float inv0 = sc.inv[0] / wc0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
+            Dout[(int64_t)(i * P + p) * n + c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
+        }
+}
+
 template <int D, typename H, int RM, int VEC, bool MU>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
@@ -395,25 +422,142 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         }
         float out[Q][P];
         collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-        // encode: moments of the post-collision state, then deviations
-        float rho2[P], K2[D], Lam2[P], Bb2[D];
-        moments<D, float>(out, rho2, K2);
+        dev_store<D, H>(out, cl2, wc0, sc, g.n, C.c, Mout, Dout);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched persistent stream-collide: many independent lattices per launch
+// ---------------------------------------------------------------------------
+// One descriptor per resident lattice.  Work items are (lattice, tile) pairs
+// numbered by the prefix tile_base; a persistent grid strides over them.  The
+// per-cell code is the same inline code as the single-lattice kernels, so a
+// lattice advanced here is bit-identical to the same lattice stepped alone.
+// Lattices carry no current source and mu == 1 (the serving workload).
+struct BatchGrid {
+    void* buf[2];        // plain: population copies; dev: moment arrays
+    void* dev[2];        // dev: deviation arrays (unused for plain)
+    const void* cl2;
+    Geo geo;             // VEC = 1 tiling, no XCD remap, no strip order
+    DevScale sc;
+    double omega;
+    int tau_half;
+    int cur0;            // copy holding the state when the tick starts
+    int fresh;           // state in the natural layout (first step)
+    int nsteps;          // steps of this lattice in this tick
+    int tile_base;       // first work item of this lattice
+    int pad;
+};
+
+struct BatchHdr {
+    int count;           // lattices in the table
+    int total_tiles;
+};
+
+__device__ __forceinline__ int batch_find(const BatchGrid* __restrict__ tab, int count, int w)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].tile_base <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D, typename T, int RM>
+__device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, int k)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    const Geo& g = G.geo;
+    int tx, ty, z;
+    tile_coords(g, tile, tx, ty, z);
+    const int bx = 1 << g.bx_shift;
+    const int x = tx * bx + (threadIdx.x & (bx - 1));
+    const int y = ty * (NT >> g.bx_shift) + (threadIdx.x >> g.bx_shift);
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = (G.cur0 + k) & 1;
+    const T* src = (const T*)G.buf[s];
+    T* dst = (T*)G.buf[s ^ 1];
+    const Cell C = make_cell(g, x, y, z);
+    T f[Q][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) Lam2[p] = cl2 * rho2[p];
+    for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int b = 0; b < D; ++b) Bb2[b] = D == 2 ? K2[b] : 0.5f * K2[b];
+        for (int p = 0; p < P; ++p)
+            f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+    const T cl2 = ((const T*)G.cl2)[C.c];
+    T rho[P], K[D], Sp[P];
+    moments<D, T>(f, rho, K);
 #pragma unroll
-        for (int p = 0; p < P; ++p) Mout[(int64_t)p * g.n + C.c] = Lam2[p];
+    for (int p = 0; p < P; ++p) Sp[p] = T(0);
+    T out[Q][P];
+    collide<D, T>(f, cl2, Sp, false, (T)G.omega, G.tau_half != 0, rho, K, out);
 #pragma unroll
-        for (int b = 0; b < D; ++b) Mout[(int64_t)(P + b) * g.n + C.c] = Bb2[b];
-        const float inv0 = sc.inv[0] / wc0;
+    for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
+        for (int p = 0; p < P; ++p) dst[(int64_t)(i * P + p) * g.n + C.c] = out[i][p];
+}
+
+template <int D, typename H, int RM>
+__device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int k)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    const Geo& g = G.geo;
+    int tx, ty, z;
+    tile_coords(g, tile, tx, ty, z);
+    const int bx = 1 << g.bx_shift;
+    const int x = tx * bx + (threadIdx.x & (bx - 1));
+    const int y = ty * (NT >> g.bx_shift) + (threadIdx.x >> g.bx_shift);
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = (G.cur0 + k) & 1;
+    const float* Min = (const float*)G.buf[s];
+    const H* Din = (const H*)G.dev[s];
+    float* Mout = (float*)G.buf[s ^ 1];
+    H* Dout = (H*)G.dev[s ^ 1];
+    const Cell C = make_cell(g, x, y, z);
+    const float cl2 = ((const float*)G.cl2)[C.c];
+    const float wc0 = 1.f / cl2 - float(D);
+    float f[Q][P];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
-                Dout[(int64_t)(i * P + p) * g.n + C.c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
-            }
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0, G.sc);
+    float rho[P], K[D], Sp[P];
+    moments<D, float>(f, rho, K);
+#pragma unroll
+    for (int p = 0; p < P; ++p) Sp[p] = 0.f;
+    float out[Q][P];
+    collide<D, float>(f, cl2, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, out);
+    dev_store<D, H>(out, cl2, wc0, G.sc, g.n, C.c, Mout, Dout);
+}
+
+// Launch k of a tick: every lattice with k < nsteps advances one step.
+template <int D, typename T>
+__global__ __launch_bounds__(NT) void k_step_batch_plain(const BatchHdr* __restrict__ hdr,
+                                                        const BatchGrid* __restrict__ tab, int k)
+{
+    const int count = hdr->count, total = hdr->total_tiles;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int gi = batch_find(tab, count, w);
+        const BatchGrid& G = tab[gi];
+        if (k >= G.nsteps) continue;
+        if (G.fresh && k == 0) batch_tile_plain<D, T, R_LOCAL>(G, w - G.tile_base, k);
+        else batch_tile_plain<D, T, R_PULL>(G, w - G.tile_base, k);
+    }
+}
+
+template <int D, typename H>
+__global__ __launch_bounds__(NT) void k_step_batch_dev(const BatchHdr* __restrict__ hdr,
+                                                      const BatchGrid* __restrict__ tab, int k)
+{
+    const int count = hdr->count, total = hdr->total_tiles;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int gi = batch_find(tab, count, w);
+        const BatchGrid& G = tab[gi];
+        if (k >= G.nsteps) continue;
+        if (G.fresh && k == 0) batch_tile_dev<D, H, R_LOCAL>(G, w - G.tile_base, k);
+        else batch_tile_dev<D, H, R_PULL>(G, w - G.tile_base, k);
     }
 }
 

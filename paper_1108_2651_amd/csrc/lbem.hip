@@ -119,6 +119,7 @@ struct lbem_s {
     int64_t t;
     bool have_medium, have_fields;
     Impl* impl;
+    hipEvent_t sync_ev;      // orders this handle's stream against batch ticks
 };
 
 #define HIP_OK(x)                                  \
@@ -429,6 +430,10 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
         if (!(h->dev_field_scale > 0.0)) h->dev_field_scale = 1.0;
     }
     h->impl = make_impl(h->D, h->prec);
+    if (h->impl && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
+        delete h->impl;
+        h->impl = nullptr;
+    }
     if (!h->impl) {
         (void)hipFree(h->partials);
         if (h->own_mem) (void)hipFree(h->arena);
@@ -455,6 +460,7 @@ int lbem_destroy(lbem_t h)
     free_source(h);
     if (h->partials) (void)hipFree(h->partials);
     if (h->own_mem && h->arena) (void)hipFree(h->arena);
+    if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
     delete h->impl;
     delete h;
     return LBEM_OK;
@@ -691,5 +697,225 @@ int lbem_energy(lbem_t h, double out[4])
 }
 
 int64_t lbem_time(lbem_t h) { return h ? h->t : -1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched stepping of many resident lattices (serving)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int NCLASS = 8;  // (dim - 2) * 4 + prec
+constexpr int BATCH_BLOCKS = 1024;
+
+int class_of(const lbem_s* h) { return (h->D - 2) * 4 + h->prec; }
+
+size_t class_bytes(int max_grids) { return align256(sizeof(BatchHdr)) + align256(sizeof(BatchGrid) * (size_t)max_grids); }
+}  // namespace
+
+struct lbem_batch_s {
+    hipStream_t stream;
+    int max_grids, ksteps;
+    char* dev;                 // NCLASS x (header, table)
+    char* pinned[2];
+    hipEvent_t ev[2];
+    int ring;
+    // graphs cached by the mask of non-empty classes
+    std::vector<std::pair<unsigned, hipGraphExec_t>> graphs;
+    std::vector<hipGraph_t> raw;
+    int use_graph;
+    hipEvent_t tick_ev;        // end of the last enqueued tick
+};
+
+static void launch_class(lbem_batch_s* b, int c, int k)
+{
+    const size_t cb = class_bytes(b->max_grids);
+    const BatchHdr* hdr = (const BatchHdr*)(b->dev + c * cb);
+    const BatchGrid* tab = (const BatchGrid*)(b->dev + c * cb + align256(sizeof(BatchHdr)));
+    dim3 g(BATCH_BLOCKS), t(NT);
+    switch (c) {
+        case 0: hipLaunchKernelGGL((k_step_batch_plain<2, double>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 1: hipLaunchKernelGGL((k_step_batch_plain<2, float>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 2: hipLaunchKernelGGL((k_step_batch_dev<2, __half>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 3: hipLaunchKernelGGL((k_step_batch_dev<2, __hip_bfloat16>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 4: hipLaunchKernelGGL((k_step_batch_plain<3, double>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 5: hipLaunchKernelGGL((k_step_batch_plain<3, float>), g, t, 0, b->stream, hdr, tab, k); break;
+        case 6: hipLaunchKernelGGL((k_step_batch_dev<3, __half>), g, t, 0, b->stream, hdr, tab, k); break;
+        default: hipLaunchKernelGGL((k_step_batch_dev<3, __hip_bfloat16>), g, t, 0, b->stream, hdr, tab, k); break;
+    }
+}
+
+static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
+{
+    if (b->use_graph) {
+        for (auto& e : b->graphs)
+            if (e.first == mask) return hipGraphLaunch(e.second, b->stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < b->ksteps; ++k)
+                for (int c = 0; c < NCLASS; ++c)
+                    if (mask & (1u << c)) launch_class(b, c, k);
+            e = hipStreamEndCapture(b->stream, &graph);
+        }
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            b->use_graph = 0;  // fall back to direct launches of the same kernels
+        } else {
+            b->graphs.push_back({mask, exec});
+            b->raw.push_back(graph);
+            return hipGraphLaunch(exec, b->stream);
+        }
+    }
+    for (int k = 0; k < b->ksteps; ++k)
+        for (int c = 0; c < NCLASS; ++c)
+            if (mask & (1u << c)) launch_class(b, c, k);
+    return hipGetLastError();
+}
+
+extern "C" {
+
+int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_batch_t* out)
+{
+    if (!out || max_lattices < 1 || max_lattices > 65536 || steps_per_tick < 1 || steps_per_tick > 4096)
+        return LBEM_EINVAL;
+    *out = nullptr;
+    if (!stream) return LBEM_EINVAL;  // a capturable stream is required
+    lbem_batch_s* b = new (std::nothrow) lbem_batch_s();
+    if (!b) return LBEM_ENOMEM;
+    b->stream = (hipStream_t)stream;
+    b->max_grids = max_lattices;
+    b->ksteps = steps_per_tick;
+    b->ring = 0;
+    b->use_graph = env_int("LBEM_BATCH_GRAPH", 1);
+    const size_t bytes = class_bytes(max_lattices) * NCLASS;
+    b->dev = nullptr;
+    b->pinned[0] = b->pinned[1] = nullptr;
+    b->ev[0] = b->ev[1] = nullptr;
+    b->tick_ev = nullptr;
+    bool ok = hipMalloc((void**)&b->dev, bytes) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&b->pinned[0], bytes, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&b->pinned[1], bytes, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->tick_ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        std::memset(b->pinned[0], 0, bytes);
+        std::memset(b->pinned[1], 0, bytes);
+        ok = hipMemcpyAsync(b->dev, b->pinned[0], bytes, hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+             hipEventRecord(b->ev[0], b->stream) == hipSuccess;
+    }
+    if (!ok) {
+        (void)lbem_batch_destroy(b);
+        return LBEM_ENOMEM;
+    }
+    *out = b;
+    return LBEM_OK;
+}
+
+int lbem_batch_destroy(lbem_batch_t b)
+{
+    if (!b) return LBEM_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& e : b->graphs) (void)hipGraphExecDestroy(e.second);
+    for (auto g : b->raw) (void)hipGraphDestroy(g);
+    for (int i = 0; i < 2; ++i) {
+        if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+        if (b->pinned[i]) (void)hipHostFree(b->pinned[i]);
+    }
+    if (b->tick_ev) (void)hipEventDestroy(b->tick_ev);
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+    return LBEM_OK;
+}
+
+int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count)
+{
+    if (!b || count < 0 || count > b->max_grids || (count > 0 && (!handles || !nsteps))) return LBEM_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const lbem_s* h = handles[i];
+        if (!h || nsteps[i] < 0 || nsteps[i] > b->ksteps) return LBEM_EINVAL;
+        if (h->nsrc != 0 || h->mu_set || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+        if (!h->have_fields) return LBEM_ESTATE;
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == h) return LBEM_EINVAL;
+    }
+    // the staging slot is free once its previous upload has executed
+    if (hipEventSynchronize(b->ev[b->ring]) != hipSuccess) return LBEM_EDEVICE;
+    char* host = b->pinned[b->ring];
+    const size_t cb = class_bytes(b->max_grids);
+    int cnt[NCLASS] = {0}, tiles[NCLASS] = {0};
+    unsigned mask = 0;
+    for (int i = 0; i < count; ++i) {
+        lbem_s* h = handles[i];
+        if (nsteps[i] == 0) continue;
+        const int c = class_of(h);
+        BatchGrid* tab = (BatchGrid*)(host + c * cb + align256(sizeof(BatchHdr)));
+        BatchGrid& G = tab[cnt[c]++];
+        std::memset(&G, 0, sizeof(G));
+        if (h->prec <= LBEM_F32) {
+            G.buf[0] = h->pop[0];
+            G.buf[1] = h->pop[1];
+        } else {
+            const size_t moff = align256((size_t)(h->P + h->D) * h->n * 4);
+            G.buf[0] = h->pop[0];
+            G.buf[1] = h->pop[1];
+            G.dev[0] = h->pop[0] + moff;
+            G.dev[1] = h->pop[1] + moff;
+        }
+        G.cl2 = h->cl2;
+        Geo& g = G.geo;
+        g = h->geo;
+        const int bx = 1 << g.bx_shift, rb = NT / bx;
+        g.tiles_y = (g.ny + rb - 1) / rb;
+        g.nblocks = g.tiles_x * g.tiles_y * g.nz;
+        g.xcd = 0;
+        g.strip = 0;
+        G.sc = h->sc;
+        G.omega = 1.0 / h->cfg.tau;
+        G.tau_half = h->cfg.tau == 0.5;
+        G.cur0 = h->cur;
+        G.fresh = h->layout == LAYOUT_NATURAL;
+        G.nsteps = (int)nsteps[i];
+        G.tile_base = tiles[c];
+        tiles[c] += g.nblocks;
+        mask |= 1u << c;
+    }
+    for (int c = 0; c < NCLASS; ++c) {
+        BatchHdr* hd = (BatchHdr*)(host + c * cb);
+        hd->count = cnt[c];
+        hd->total_tiles = tiles[c];
+    }
+    // members set up on other streams: their work so far precedes the tick
+    for (int i = 0; i < count; ++i) {
+        lbem_s* h = handles[i];
+        if (nsteps[i] == 0 || h->stream == b->stream) continue;
+        if (hipEventRecord(h->sync_ev, h->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, h->sync_ev, 0) != hipSuccess)
+            return LBEM_EDEVICE;
+    }
+    if (hipMemcpyAsync(b->dev, host, cb * NCLASS, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return LBEM_EDEVICE;
+    if (hipEventRecord(b->ev[b->ring], b->stream) != hipSuccess) return LBEM_EDEVICE;
+    b->ring ^= 1;
+    if (mask && enqueue_tick(b, mask) != hipSuccess) return LBEM_EDEVICE;
+    // ... and later work on a member's own stream (moments, destroy) follows it
+    if (hipEventRecord(b->tick_ev, b->stream) != hipSuccess) return LBEM_EDEVICE;
+    for (int i = 0; i < count; ++i) {
+        lbem_s* h = handles[i];
+        if (nsteps[i] == 0 || h->stream == b->stream) continue;
+        if (hipStreamWaitEvent(h->stream, b->tick_ev, 0) != hipSuccess) return LBEM_EDEVICE;
+    }
+    for (int i = 0; i < count; ++i) {
+        lbem_s* h = handles[i];
+        if (nsteps[i] == 0) continue;
+        if (nsteps[i] & 1) h->cur = 1 - h->cur;
+        h->layout = LAYOUT_PULL_PENDING;
+        h->t += nsteps[i];
+    }
+    return LBEM_OK;
+}
 
 }  // extern "C"

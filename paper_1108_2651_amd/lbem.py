@@ -23,7 +23,7 @@ STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 # every entry point of include/lbem.h
 SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_medium",
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
-           "lbem_time", "lbem_strerror")
+           "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy")
 
 
 class Config(C.Structure):

@@ -1,0 +1,102 @@
+"""Batched stepping and continuous-batching serving on the GPU: every lattice
+advanced in a batch (and every request served in a mix) is bit-identical to
+the same lattice stepped alone."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, random_problem
+from paper_1108_2651_amd import inputs, lbem, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _solo(p, prec, nsteps):
+    s = lbem.Solver(p.dim, p.shape, prec, streaming="pull")
+    s.setup(p)
+    s.step(nsteps)
+    out = s.moments()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batch_matches_standalone_bitwise(graph):
+    import torch
+    os.environ["LBEM_BATCH_GRAPH"] = graph
+    try:
+        st = torch.cuda.Stream()
+        batch = serve.Batch(16, 7, st)
+    finally:
+        os.environ.pop("LBEM_BATCH_GRAPH", None)
+    cases = [(2, (96, 40, 1), "f32"), (2, (33, 17, 1), "f64"), (2, (130, 64, 1), "f16dev"),
+             (3, (20, 12, 9), "f32"), (3, (16, 16, 16), "bf16dev"), (3, (9, 7, 5), "f64"),
+             (3, (24, 20, 12), "f16dev"), (2, (64, 64, 1), "bf16dev")]
+    probs, solvers = [], []
+    other = torch.cuda.Stream()
+    for k, (dim, shape, prec) in enumerate(cases):
+        p = random_problem(dim, shape, seed=200 + k, src=False)
+        # half of the members live on another stream than the batch
+        s = lbem.Solver(dim, shape, prec, streaming="pull", stream=st if k % 2 == 0 else other)
+        s.setup(p)
+        probs.append(p)
+        solvers.append(s)
+    plan = [[7, 3, 7, 0, 5, 7, 1, 7], [7, 7, 0, 7, 7, 2, 7, 7], [1, 7, 7, 7, 0, 7, 7, 4]]
+    total = np.sum(plan, axis=0)
+    for ns in plan:
+        batch.run(solvers, ns)
+    for k, (dim, shape, prec) in enumerate(cases):
+        announce(f"batch vs solo graph={graph} {dim}d {shape} {prec} steps={total[k]}")
+        got = solvers[k].moments()
+        assert solvers[k].t == total[k]
+        want = _solo(probs[k], prec, int(total[k]))
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    for s in solvers:
+        s.close()
+    batch.close()
+
+
+def test_batch_rejects_unsupported_members():
+    import torch
+    st = torch.cuda.Stream()
+    b = serve.Batch(4, 5, st)
+    p = random_problem(2, (32, 16, 1), seed=1, src=True, nsteps=4)
+    s = lbem.Solver(2, p.shape, "f32", streaming="pull", stream=st)
+    s.setup(p)                                  # has a current source
+    with pytest.raises(lbem.LbemError) as e:
+        b.run([s], [3])
+    assert e.value.code == lbem.LBEM_EINVAL
+    s2 = lbem.Solver(2, p.shape, "f32", streaming="pull", stream=st)
+    with pytest.raises(lbem.LbemError) as e:
+        b.run([s2], [3])                        # not initialised
+    assert e.value.code == lbem.LBEM_ESTATE
+    q = random_problem(2, (32, 16, 1), seed=2, src=False)
+    s3 = lbem.Solver(2, q.shape, "f32", streaming="pull", stream=st)
+    s3.setup(q)
+    with pytest.raises(lbem.LbemError):
+        b.run([s3, s3], [1, 1])                 # duplicate member
+    with pytest.raises(lbem.LbemError):
+        b.run([s3], [6])                        # more than steps_per_tick
+    b.close()
+
+
+def test_serving_mix_results_equal_solo_runs():
+    reqs = serve.make_requests(count=20, rate=400.0, seed=11, steps_lo=30, steps_hi=160,
+                               side2d=(5, 7.5), side3d=(4, 5.5))
+    announce("serving mix of 20 requests")
+    rep = serve.serve(reqs, budget_bytes=64 << 20, max_slots=8, steps_per_tick=16, workers=3,
+                      keep_results=True)
+    announce(f"  completed={rep.completed} p50={rep.p50_ms:.1f} ms p99={rep.p99_ms:.1f} ms "
+             f"mean resident={rep.mean_resident:.1f}")
+    assert rep.completed == len(reqs)
+    assert rep.max_resident > 1                 # requests really shared ticks
+    ex = serve.GpuExecutor(4, 16, workers=1)
+    try:
+        for r in reqs:
+            p = serve.request_problem_fast(r, ex)
+            want = _solo(p, r.prec, r.nsteps)
+            got = r.result
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), r.rid
+    finally:
+        ex.close()
