@@ -307,6 +307,121 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
 }
 
 // ---------------------------------------------------------------------------
+// 2D temporal blocking: NS time steps per launch (plain formats, pull)
+// ---------------------------------------------------------------------------
+// A block owns an output tile of TXF x TY cells.  All work happens in one LDS
+// frame: the tile grown by H = NS-1 cells on every side.  Step 1 pulls the
+// stored populations from HBM for the whole frame and collides; steps 2..NS
+// pull from the previous LDS layer, each on a region one cell smaller, the
+// last one on the tile itself, which is written back.  State bytes therefore
+// cross HBM once per NS steps; every cell update runs the same collide() code
+// as the single-step kernel, so NS fused steps equal NS single steps bit for
+// bit.  Periodic wrap is applied to the frame's global coordinates.
+constexpr int TXF = 64;
+
+template <typename T>
+struct FusedSrc {
+    const int* off;      // per tile range into ent/val (nullptr: no source)
+    const int2* ent;     // (frame cell index, pair)
+    const T* val;        // S per unit amplitude
+};
+
+template <typename T, int NS>
+struct AmpPack {
+    T a[NS];             // source amplitude of each fused step
+};
+
+template <typename T, int NS, int TY>
+__global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
+                                                    const Geo g, const FusedSrc<T> fs, const AmpPack<T, NS> amps,
+                                                    const T omega, const int tau_half)
+{
+    constexpr int H = NS - 1;
+    constexpr int W = TXF + 2 * H;          // frame width
+    constexpr int FH = TY + 2 * H;          // frame height
+    constexpr int FC = W * FH;
+    constexpr int NB = NS > 2 ? 2 : 1;      // LDS population layers
+    constexpr int Q = 5;
+    __shared__ T lp[NB][Q][FC];
+    __shared__ T lc[FC];
+    __shared__ T ls[FC];
+
+    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tx = b % g.tiles_x, ty = b / g.tiles_x;
+    const int x0 = tx * TXF - H, y0 = ty * TY - H;     // global coords of frame (0,0)
+
+    // source coefficients of the frame (tiles that own none skip this)
+    bool has_src = false;
+    if (fs.off) {
+        const int s0 = fs.off[b], s1 = fs.off[b + 1];
+        if (s1 > s0) {
+            has_src = true;
+            for (int k = threadIdx.x; k < FC; k += NT) ls[k] = T(0);
+            __syncthreads();
+            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+                const int2 e = fs.ent[k];
+                ls[e.x] = fs.val[k];
+            }
+            __syncthreads();
+        }
+    }
+
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        const int r = H - st;               // region = tile grown by r
+        const int wr = TXF + 2 * r, hr = TY + 2 * r, off = H - r;
+        const T amp = has_src ? amps.a[st] : T(0);
+        const int in = (st - 1) % NB, out = st % NB;
+        for (int k = threadIdx.x; k < wr * hr; k += NT) {
+            const int fx = off + k % wr, fy = off + k / wr;
+            const int f = fy * W + fx;
+            T fv[Q][1];
+            T cl2;
+            int gcell = 0;
+            bool store_global = false;
+            if (st == 0) {
+                int gx = (x0 + fx) % g.nx, gy = (y0 + fy) % g.ny;
+                if (gx < 0) gx += g.nx;
+                if (gy < 0) gy += g.ny;
+                const Cell C = make_cell(g, gx, gy, 0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) fv[i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
+                cl2 = cl2a[C.c];
+                lc[f] = cl2;
+            } else {
+                // pull from the previous layer: x - c_i in frame coordinates
+                fv[0][0] = lp[in][0][f];
+                fv[1][0] = lp[in][1][f - 1];
+                fv[2][0] = lp[in][2][f - W];
+                fv[3][0] = lp[in][3][f + 1];
+                fv[4][0] = lp[in][4][f + W];
+                cl2 = lc[f];
+                if (st == NS - 1) {
+                    const int gx = x0 + fx, gy = y0 + fy;    // inside the tile: no wrap needed
+                    store_global = gx < g.nx && gy < g.ny;
+                    gcell = gx + g.nx * gy;
+                }
+            }
+            T rho[1], K[2], Sp[1];
+            moments<2, T>(fv, rho, K);
+            Sp[0] = has_src ? ls[f] * amp : T(0);
+            T o[Q][1];
+            collide<2, T>(fv, cl2, Sp, has_src, omega, tau_half != 0, rho, K, o);
+            if (st == NS - 1) {
+                if (store_global) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.n + gcell] = o[i][0];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lp[out][i][f] = o[i][0];
+            }
+        }
+        if (st < NS - 1) __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // deviation storage: FP32 moments + 16-bit scaled deviations, FP32 arithmetic
 // ---------------------------------------------------------------------------
 template <typename H>

@@ -111,6 +111,13 @@ struct lbem_s {
     // tiling of the step kernels
     Geo geo;
     int vec;
+    // 2D temporal blocking (fuse_ns steps per launch; 1 = off)
+    int fuse_ns, fuse_ty;
+    Geo fgeo;
+    int* fsrc_off;
+    int2* fsrc_ent;
+    void* fsrc_val;
+    int64_t nfsrc;
     // deviation scales
     DevScale sc;
     double wc0_max;
@@ -134,6 +141,8 @@ struct lbem_s {
 struct Impl {
     virtual ~Impl() {}
     virtual hipError_t step(lbem_s* h, double amp) = 0;
+    // advance h->fuse_ns steps in one launch (only when fused_ok and pull-pending)
+    virtual hipError_t step_fused(lbem_s* h, const double* amp) { return hipErrorInvalidValue; }
     virtual hipError_t fields(lbem_s* h, double* E, double* B, double* partials) = 0;
     virtual hipError_t init(lbem_s* h, const double* dE, const double* dB) = 0;
     virtual hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) = 0;
@@ -163,6 +172,45 @@ static hipError_t launch_fields(lbem_s* h, const R& rd, double* E, double* B, do
     hipLaunchKernelGGL((k_fields<D, TM, R>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, rd,
                        (const TM*)h->cl2, h->mu_set ? h->mu_r : nullptr, geo1(h), E, B, partials);
     return hipGetLastError();
+}
+
+// fused 2D launches: (steps per launch, tile rows) pairs that are instantiated
+template <typename T, int NS, int TY>
+static hipError_t go_fused_nt(lbem_s* h, const T* src, T* dst, const double* amp)
+{
+    FusedSrc<T> fs;
+    fs.off = h->nfsrc ? h->fsrc_off : nullptr;
+    fs.ent = h->fsrc_ent;
+    fs.val = (const T*)h->fsrc_val;
+    AmpPack<T, NS> a;
+    for (int j = 0; j < NS; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
+    hipLaunchKernelGGL((k_step_fused2d<T, NS, TY>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src, dst,
+                       (const T*)h->cl2, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau), (int)(h->cfg.tau == 0.5));
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t go_fused(lbem_s* h, const T* src, T* dst, const double* amp)
+{
+    const int ns = h->fuse_ns, ty = h->fuse_ty;
+    if constexpr (sizeof(T) == 4) {
+        if (ns == 2 && ty == 16) return go_fused_nt<T, 2, 16>(h, src, dst, amp);
+        if (ns == 2 && ty == 8) return go_fused_nt<T, 2, 8>(h, src, dst, amp);
+        if (ns == 2 && ty == 4) return go_fused_nt<T, 2, 4>(h, src, dst, amp);
+        if (ns == 3 && ty == 16) return go_fused_nt<T, 3, 16>(h, src, dst, amp);
+        if (ns == 4 && ty == 16) return go_fused_nt<T, 4, 16>(h, src, dst, amp);
+        if (ns == 4 && ty == 8) return go_fused_nt<T, 4, 8>(h, src, dst, amp);
+    } else {
+        if (ns == 2 && ty == 8) return go_fused_nt<T, 2, 8>(h, src, dst, amp);
+        if (ns == 2 && ty == 4) return go_fused_nt<T, 2, 4>(h, src, dst, amp);
+        if (ns == 3 && ty == 8) return go_fused_nt<T, 3, 8>(h, src, dst, amp);
+    }
+    return hipErrorInvalidValue;
+}
+
+static bool fused_ok(const lbem_s* h)
+{
+    return h->D == 2 && h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && !h->mu_set && h->fuse_ns > 1;
 }
 
 template <int D, typename T>
@@ -213,6 +261,17 @@ struct PlainImpl : Impl {
         h->cur = 1 - h->cur;
         h->layout = LAYOUT_PULL_PENDING;
         return e;
+    }
+    hipError_t step_fused(lbem_s* h, const double* amp) override
+    {
+        if constexpr (D == 2) {
+            const T* a = (const T*)h->pop[h->cur];
+            T* b = (T*)h->pop[1 - h->cur];
+            hipError_t e = go_fused<T>(h, a, b, amp);
+            h->cur = 1 - h->cur;
+            return e;
+        }
+        return hipErrorInvalidValue;
     }
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
@@ -339,6 +398,25 @@ static void make_geo(lbem_s* h)
     if (g.strip <= 0 || nz == 1 || g.strip >= g.tiles_y || g.tiles_y % g.strip != 0) g.strip = 0;
 }
 
+static void make_fused_geo(lbem_s* h)
+{
+    const bool f64 = h->prec == LBEM_F64;
+    h->fuse_ns = env_int("LBEM_FUSE", 2);
+    h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : 8);
+    // only the instantiated (steps, rows) pairs; anything else runs single steps
+    const int ns = h->fuse_ns, ty = h->fuse_ty;
+    const bool ok = f64 ? ((ns == 2 && (ty == 8 || ty == 4)) || (ns == 3 && ty == 8))
+                        : ((ns == 2 && (ty == 16 || ty == 8 || ty == 4)) || (ns == 3 && ty == 16) ||
+                           (ns == 4 && (ty == 16 || ty == 8)));
+    if (!ok) h->fuse_ns = 1;
+    Geo& g = h->fgeo;
+    g = h->geo;
+    g.tiles_x = (g.nx + TXF - 1) / TXF;
+    g.tiles_y = (g.ny + h->fuse_ty - 1) / h->fuse_ty;
+    g.nblocks = g.tiles_x * g.tiles_y;
+    g.strip = 0;
+}
+
 // inverse of tile_coords()
 static int tile_id(const Geo& g, int tx, int ty, int z)
 {
@@ -423,6 +501,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     if (h->D == 3 && h->vec == 4) h->vec = 2;
     if (cfg->mu_varies) h->vec = 1;
     make_geo(h);
+    make_fused_geo(h);
     for (int i = 0; i < 7; ++i) { h->sc.s[i] = 1.f; h->sc.inv[i] = 1.f; }
     {
         const char* v = std::getenv("LBEM_DEV_FIELD_SCALE");
@@ -449,8 +528,61 @@ static void free_source(lbem_s* h)
     if (h->src_off) (void)hipFree(h->src_off);
     if (h->src_ent) (void)hipFree(h->src_ent);
     if (h->src_val) (void)hipFree(h->src_val);
+    if (h->fsrc_off) (void)hipFree(h->fsrc_off);
+    if (h->fsrc_ent) (void)hipFree(h->fsrc_ent);
+    if (h->fsrc_val) (void)hipFree(h->fsrc_val);
     h->src_off = nullptr; h->src_ent = nullptr; h->src_val = nullptr;
+    h->fsrc_off = nullptr; h->fsrc_ent = nullptr; h->fsrc_val = nullptr;
     h->nsrc = 0;
+    h->nfsrc = 0;
+}
+
+// Per-tile source entries of the fused 2D tiling: every frame cell (tile plus
+// halo, periodic images included) that carries a current.
+static int build_fused_source(lbem_s* h, const std::vector<double>& dense)
+{
+    const Geo& g = h->fgeo;
+    const int H = h->fuse_ns - 1, TY = h->fuse_ty;
+    const int W = TXF + 2 * H, FH = TY + 2 * H;
+    std::vector<int> off(g.nblocks + 1, 0);
+    std::vector<int2> ent;
+    std::vector<double> val;
+    for (int b = 0; b < g.nblocks; ++b) {
+        const int tx = b % g.tiles_x, ty = b / g.tiles_x;
+        const int x0 = tx * TXF - H, y0 = ty * TY - H;
+        for (int fy = 0; fy < FH; ++fy) {
+            int gy = (y0 + fy) % g.ny;
+            if (gy < 0) gy += g.ny;
+            for (int fx = 0; fx < W; ++fx) {
+                int gx = (x0 + fx) % g.nx;
+                if (gx < 0) gx += g.nx;
+                const double v = dense[(size_t)gx + (size_t)g.nx * gy];
+                if (v != 0.0) {
+                    ent.push_back(make_int2(fy * W + fx, 0));
+                    val.push_back(v);
+                }
+            }
+        }
+        off[b + 1] = (int)ent.size();
+    }
+    const size_t ms = ent.size(), tv = h->prec == LBEM_F64 ? 8 : 4;
+    if (hipMalloc((void**)&h->fsrc_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->fsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->fsrc_val, std::max<size_t>(ms, 1) * tv) != hipSuccess)
+        return LBEM_ENOMEM;
+    hipError_t e = hipMemcpy(h->fsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->fsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) {
+        if (tv == 8) {
+            e = hipMemcpy(h->fsrc_val, val.data(), ms * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> f(val.begin(), val.end());
+            e = hipMemcpy(h->fsrc_val, f.data(), ms * 4, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->nfsrc = (int64_t)ms;
+    return LBEM_OK;
 }
 
 int lbem_destroy(lbem_t h)
@@ -596,7 +728,9 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     const int bx = 1 << g.bx_shift, rb = NT / bx;
     struct Item { int b; int local; double v; };
     std::vector<Item> items;
+    std::vector<double> src_value;
     items.reserve(merged.size());
+    src_value.reserve(merged.size());
     for (auto& e : merged) {
         const int c = (int)e.first;
         const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
@@ -608,6 +742,7 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
         // S per unit amplitude on pair pp: sgn * (-weight/eps_abs)
         const double eps_abs = (double)(D - 1) / (mu[c] * cl2[c]);
         items.push_back({b, local, -(double)sg * e.second / eps_abs});
+        src_value.push_back(items.back().v);
     }
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.b < b.b; });
     std::vector<int> off(g.nblocks + 1, 0);
@@ -638,6 +773,12 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     }
     if (e != hipSuccess) { free_source(h); return LBEM_EDEVICE; }
     h->nsrc = (int64_t)ms;
+    if (D == 2 && h->prec <= LBEM_F32 && h->fuse_ns > 1) {
+        std::vector<double> dense((size_t)n, 0.0);
+        for (size_t k = 0; k < merged.size(); ++k) dense[(size_t)merged[k].first] = src_value[k];
+        const int rc = build_fused_source(h, dense);
+        if (rc != LBEM_OK) { free_source(h); return rc; }
+    }
     return LBEM_OK;
 }
 
@@ -645,10 +786,19 @@ int lbem_step(lbem_t h, int64_t nsteps, const double* amp)
 {
     if (!h || nsteps < 0) return LBEM_EINVAL;
     if (!h->have_fields) return LBEM_ESTATE;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    const bool fuse = fused_ok(h);
+    int64_t k = 0;
+    while (k < nsteps) {
+        if (fuse && h->layout == LAYOUT_PULL_PENDING && nsteps - k >= h->fuse_ns) {
+            if (h->impl->step_fused(h, (amp && h->nsrc) ? amp + k : nullptr) != hipSuccess) return LBEM_EDEVICE;
+            k += h->fuse_ns;
+            h->t += h->fuse_ns;
+            continue;
+        }
         const double a = (amp && h->nsrc) ? amp[k] : 0.0;
         if (h->impl->step(h, a) != hipSuccess) return LBEM_EDEVICE;
         h->t += 1;
+        ++k;
     }
     return LBEM_OK;
 }

@@ -160,19 +160,35 @@ class Scheduler:
         done: list = []
         t0 = ex.now()
 
+        finishing = {}               # request -> (read-back future or None, final status)
+
         def release(r, status):
+            # read back / free off the scheduler thread; memory counts until done
+            fut = ex.finish_async(r.slot, want=(status == "done")) if r.slot is not None else None
+            r.slot = None
+            finishing[r] = (fut, status)
+
+        def reap(block=False):
             nonlocal used
-            if r.slot is not None:
-                res = ex.finish(r.slot, want=(status == "done"))
+            if block and finishing:
+                futs = [f for f, _ in finishing.values() if f is not None]
+                if futs and not any(ex.ready(f) for f in futs):
+                    ex.wait_any(futs)
+            for r in list(finishing):
+                fut, status = finishing[r]
+                if fut is not None and not ex.ready(fut):
+                    continue
+                del finishing[r]
+                res, t_abs = ex.result(fut) if fut is not None else (None, ex.now())
                 if status == "done" and self.keep:
                     r.result = res
-                r.slot = None
-            used -= r.nbytes
-            r.t_done = ex.now() - t0
-            r.status = status
-            done.append(r)
+                used -= r.nbytes
+                r.t_done = t_abs - t0
+                r.status = status
+                done.append(r)
 
-        while arrivals or pending or setting_up or active or inflight:
+        while arrivals or pending or setting_up or active or inflight or finishing:
+            reap()
             now = ex.now() - t0
             while arrivals and arrivals[0].t_arrive <= now:
                 pending.append(arrivals.popleft())
@@ -233,9 +249,13 @@ class Scheduler:
             if not active and not inflight:
                 if setting_up:
                     ex.wait_any(list(setting_up.values()))
+                elif finishing:
+                    reap(block=True)
                 elif arrivals and not pending:
                     ex.sleep_until(t0 + arrivals[0].t_arrive)
                 # else: memory was just released; the next pass admits the head
+            elif pending and finishing and len(inflight) <= 1:
+                reap()
         wall = ex.now() - t0
         ok = [r for r in done if r.status == "done"]
         lat = np.array([(r.t_done - r.t_arrive) * 1e3 for r in ok]) if ok else np.zeros(1)
@@ -316,10 +336,14 @@ class GpuExecutor:
     def tick(self, slots, nsteps):
         self.batch.run(slots, nsteps)
 
-    def finish(self, s, want=True):
+    def _finish(self, s, want):
         res = s.moments() if want else None
+        t = time.perf_counter()
         s.close()
-        return res
+        return res, t
+
+    def finish_async(self, s, want=True):
+        return self.pool.submit(self._finish, s, want)
 
     def close(self):
         self.pool.shutdown(wait=True)

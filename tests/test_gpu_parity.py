@@ -75,6 +75,21 @@ def test_ragged_shapes_all_terms(dim, shape, mu):
     compare(p, 61, "f32", "auto", tol=2e-5)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(96, 40, 1), (100, 37, 1), (1, 64, 1), (300, 2, 1), (130, 70, 1)])
+def test_temporal_blocking_bitwise(prec, shape):
+    """2, 3 or 4 fused time steps per launch (LDS frame with halo, periodic
+    images of sources included) equal the same number of single steps bit for
+    bit, for ragged and tiny lattices and odd step counts."""
+    p = random_problem(2, shape, seed=sum(shape) + 11, nsteps=53)
+    ref = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": 1}).moments()
+    combos = [(2, 16), (2, 8), (2, 4), (3, 16), (4, 16), (4, 8)] if prec == "f32" else [(2, 8), (2, 4), (3, 8)]
+    for ns, ty in combos:
+        announce(f"fused {prec} {shape} ns={ns} ty={ty}")
+        got = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": ns, "LBEM_FUSE_TY": ty}).moments()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (ns, ty)
+
+
 def test_tau_not_half():
     p = random_problem(2, (40, 24, 1), seed=3, nsteps=80)
     compare(p, 80, "f64", tau=0.8)
@@ -109,7 +124,7 @@ def test_aa_pull_and_tilings_bitwise(dim):
     """In-place AA streaming, double-buffered pull, different cells-per-thread
     and block-to-XCD mappings all give bit-identical fields (race check)."""
     p = random_problem(dim, (96, 40, 1) if dim == 2 else (40, 24, 20), seed=80 + dim, nsteps=77)
-    ref = gpu_run(p, 77, "f32", "pull").moments()
+    ref = gpu_run(p, 77, "f32", "pull", env={"LBEM_FUSE": 1}).moments()
     variants = [dict(streaming="aa"), dict(streaming="pull", env={"LBEM_XCD": 0}),
                 dict(streaming="aa", env={"LBEM_VEC": 2})]
     if dim == 3:

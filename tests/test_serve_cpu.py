@@ -50,7 +50,7 @@ class FakeExecutor:
         return True
 
     def result(self, f):
-        return f.slot
+        return f.slot     # the admitted slot, or (result, completion time) of a read-back
 
     def wait_any(self, futs):
         pass
@@ -65,10 +65,10 @@ class FakeExecutor:
             work += self.live[s][0].cells * k
         self.t += work / self.rate
 
-    def finish(self, slot, want=True):
+    def finish_async(self, slot, want=True):
         r, _ = self.live.pop(slot)
         self.finished.append((r.rid, self.steps[slot], want))
-        return ("result", r.rid) if want else None
+        return _Fut((("result", r.rid) if want else None, self.t))
 
 
 def mix(count=60, rate=200.0, seed=3):
