@@ -13,11 +13,14 @@
 //   plain  : T = double or float per population.
 //   dev    : per cell the post-collision moments (Lambda_p, Bbar_b) in FP32
 //            and, per population, its deviation from the equilibrium of those
-//            moments in FP16/BF16 divided by a power-of-two scale s_i.
+//            moments in FP16/BF16, divided by a per-cell power-of-two scale
+//            times the velocity's equilibrium prefactor.
 #pragma once
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lattice.h"
 
@@ -437,13 +440,44 @@ __device__ __forceinline__ __half f2h<__half>(float v) { return __float2half_rn(
 template <>
 __device__ __forceinline__ __hip_bfloat16 f2h<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
-// Power-of-two scale per velocity: a moving population's deviation d_i is
-// stored as d_i / s_i; the rest population's as d_0 / (s_0 w0/c^2(x)), which
-// follows its local magnitude (g0_0 = (w0/c^2) Lambda) across the medium.
-struct DevScale {
-    float s[7];
-    float inv[7];
-};
+// Scale of the stored deviations.  Per cell, s(x) is the smallest power of two
+// >= max |stored moment| of that cell (its FP32 Lambda_p and Bbar_b, which the
+// writer and every reader see identically), so 16-bit precision is relative
+// to the local field whatever its absolute size.  Per velocity the scale is
+// s(x) times the equilibrium prefactor of that velocity: 1/2 for the moving
+// ones, w0/c^2(x) for the rest particle.
+__device__ __forceinline__ void pow2_scale(float m, float& s, float& inv)
+{
+    unsigned u = __float_as_uint(fabsf(m));
+    int e = (int)((u >> 23) & 0xffu);
+    if (e == 0) {               // zero or subnormal moments: unit scale
+        s = 1.f;
+        inv = 1.f;
+        return;
+    }
+    if (u & 0x7fffffu) ++e;     // round up to the next power of two
+    if (e > 253) e = 253;
+    s = __uint_as_float((unsigned)e << 23);
+    inv = __uint_as_float((unsigned)(254 - e) << 23);
+}
+
+template <int D>
+__device__ __forceinline__ float cell_magnitude(const float* M, int64_t n, int cs)
+{
+    constexpr int P = Lat<D>::P;
+    float m = 0.f;
+#pragma unroll
+    for (int q = 0; q < P + D; ++q) m = fmaxf(m, fabsf(M[(int64_t)q * n + cs]));
+    return m;
+}
+
+// 16-bit codes saturate at the largest finite value instead of overflowing
+template <typename H>
+__device__ __forceinline__ float sat16(float v)
+{
+    const float lim = sizeof(H) == 2 && std::is_same<H, __half>::value ? 65504.f : 3.0e38f;
+    return fminf(fmaxf(v, -lim), lim);
+}
 
 // equilibrium of the stored moments, as used by both the writer and readers
 template <int D>
@@ -456,7 +490,7 @@ __device__ __forceinline__ float dev_eq(int i, int p, const float (&Lam)[Lat<D>:
 // Reconstruct population (i,p) stored at cell cs (moments M, deviations Dv).
 template <int D, typename H>
 __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n, int i, int p, int cs,
-                                          float wc0_here, const DevScale& sc)
+                                          float wc0_here)
 {
     constexpr int P = Lat<D>::P;
     float Lam[P], Bb[D];
@@ -470,7 +504,9 @@ __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n
         Bb[e] = need ? M[(int64_t)(P + e) * n + cs] : 0.f;
     }
     const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0_here);
-    const float si = i == 0 ? sc.s[0] * wc0_here : sc.s[i];
+    float s, inv;
+    pow2_scale(cell_magnitude<D>(M, n, cs), s, inv);
+    const float si = i == 0 ? s * wc0_here : 0.5f * s;
     return g0 + si * h2f<H>(Dv[(int64_t)(i * P + p) * n + cs]);
 }
 
@@ -478,7 +514,7 @@ __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n
 // deviations from the equilibrium of those moments.
 template <int D, typename H>
 __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
-                                          const DevScale& sc, int64_t n, int c, float* Mout, H* Dout)
+                                          int64_t n, int c, float* Mout, H* Dout)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     float rho2[P], K2[D], Lam2[P], Bb2[D];
@@ -491,13 +527,20 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
     for (int p = 0; p < P; ++p) Mout[(int64_t)p * n + c] = Lam2[p];
 #pragma unroll
     for (int b = 0; b < D; ++b) Mout[(int64_t)(P + b) * n + c] = Bb2[b];
-    const float inv0 = sc.inv[0] / wc0;
+    float m = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p) m = fmaxf(m, fabsf(Lam2[p]));
+#pragma unroll
+    for (int b = 0; b < D; ++b) m = fmaxf(m, fabsf(Bb2[b]));
+    float s, inv;
+    pow2_scale(m, s, inv);
+    const float inv0 = inv / wc0, invm = 2.f * inv;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
-            Dout[(int64_t)(i * P + p) * n + c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
+            Dout[(int64_t)(i * P + p) * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
         }
 }
 
@@ -505,7 +548,7 @@ template <int D, typename H, int RM, int VEC, bool MU>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
-                                                const int tau_half, const DevScale sc)
+                                                const int tau_half)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ float lds[P * NT * VEC];
@@ -524,7 +567,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         for (int i = 0; i < Q; ++i)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0, sc);
+                f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
         float rho[P], K[D], Sp[P];
         moments<D, float>(f, rho, K);
 #pragma unroll
@@ -537,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         }
         float out[Q][P];
         collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-        dev_store<D, H>(out, cl2, wc0, sc, g.n, C.c, Mout, Dout);
+        dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
     }
 }
 
@@ -554,7 +597,6 @@ struct BatchGrid {
     void* dev[2];        // dev: deviation arrays (unused for plain)
     const void* cl2;
     Geo geo;             // VEC = 1 tiling, no XCD remap, no strip order
-    DevScale sc;
     double omega;
     int tau_half;
     int cur0;            // copy holding the state when the tick starts
@@ -637,14 +679,14 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int p = 0; p < P; ++p) f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0, G.sc);
+        for (int p = 0; p < P; ++p) f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
     float rho[P], K[D], Sp[P];
     moments<D, float>(f, rho, K);
 #pragma unroll
     for (int p = 0; p < P; ++p) Sp[p] = 0.f;
     float out[Q][P];
     collide<D, float>(f, cl2, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, out);
-    dev_store<D, H>(out, cl2, wc0, G.sc, g.n, C.c, Mout, Dout);
+    dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
 }
 
 // Launch k of a tick: every lattice with k < nsteps advances one step.
@@ -694,11 +736,10 @@ struct DevReader {
     const float* M;
     const H* Dv;
     int64_t n;
-    DevScale sc;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double cl2) const
     {
         const float wc0 = 1.f / (float)cl2 - float(D);
-        return (double)dev_load<D, H>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0, sc);
+        return (double)dev_load<D, H>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0);
     }
 };
 
@@ -900,8 +941,7 @@ __global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E,
 
 template <int D, typename H>
 __global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, const double* __restrict__ B,
-                                                 const float* __restrict__ cl2a, int64_t n, float* M, H* Dv,
-                                                 const DevScale sc)
+                                                 const float* __restrict__ cl2a, int64_t n, float* M, H* Dv)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -920,13 +960,20 @@ __global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, c
 #pragma unroll
     for (int b = 0; b < D; ++b) M[(int64_t)(P + b) * n + c] = Bf[b];
     const float wc0 = 1.f / cl2 - float(D);
-    const float inv0 = sc.inv[0] / wc0;
+    float m = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p) m = fmaxf(m, fabsf(Lf[p]));
+#pragma unroll
+    for (int b = 0; b < D; ++b) m = fmaxf(m, fabsf(Bf[b]));
+    float s, inv;
+    pow2_scale(m, s, inv);
+    const float inv0 = inv / wc0, invm = 2.f * inv;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const float d = (float)(g0[i][p] - (double)dev_eq<D>(i, p, Lf, Bf, wc0));
-            Dv[(int64_t)(i * P + p) * n + c] = f2h<H>(d * (i == 0 ? inv0 : sc.inv[i]));
+            Dv[(int64_t)(i * P + p) * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
         }
 }
 

@@ -118,10 +118,6 @@ struct lbem_s {
     int2* fsrc_ent;
     void* fsrc_val;
     int64_t nfsrc;
-    // deviation scales
-    DevScale sc;
-    double wc0_max;
-    double dev_field_scale;  // field magnitude assumed when E0 = B0 = 0
     // state
     int64_t t;
     bool have_medium, have_fields;
@@ -314,7 +310,7 @@ struct DevImpl : Impl {
         hipLaunchKernelGGL((k_step_dev<D, H, RM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
                            M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
-                           (int)(h->cfg.tau == 0.5), h->sc);
+                           (int)(h->cfg.tau == 0.5));
         return hipGetLastError();
     }
     template <int RM>
@@ -340,9 +336,9 @@ struct DevImpl : Impl {
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         if (h->layout == LAYOUT_NATURAL)
-            return launch_fields<D, float>(h, DevReader<D, H, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n, h->sc},
+            return launch_fields<D, float>(h, DevReader<D, H, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n},
                                            E, B, partials);
-        return launch_fields<D, float>(h, DevReader<D, H, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n, h->sc}, E,
+        return launch_fields<D, float>(h, DevReader<D, H, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n}, E,
                                        B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
@@ -350,7 +346,7 @@ struct DevImpl : Impl {
         h->cur = 0;
         h->layout = LAYOUT_NATURAL;
         hipLaunchKernelGGL((k_init_dev<D, H>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
-                           (const float*)h->cl2, h->n, M(h, 0), Dv(h, 0), h->sc);
+                           (const float*)h->cl2, h->n, M(h, 0), Dv(h, 0));
         return hipGetLastError();
     }
     hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) override
@@ -502,12 +498,6 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     if (cfg->mu_varies) h->vec = 1;
     make_geo(h);
     make_fused_geo(h);
-    for (int i = 0; i < 7; ++i) { h->sc.s[i] = 1.f; h->sc.inv[i] = 1.f; }
-    {
-        const char* v = std::getenv("LBEM_DEV_FIELD_SCALE");
-        h->dev_field_scale = (v && *v) ? std::atof(v) : 1.0;
-        if (!(h->dev_field_scale > 0.0)) h->dev_field_scale = 1.0;
-    }
     h->impl = make_impl(h->D, h->prec);
     if (h->impl && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
         delete h->impl;
@@ -607,13 +597,6 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
         for (int64_t c = 0; c < n; ++c)
             if (mu_r[c] != 1.0) { nonunit_mu = true; break; }
     if (nonunit_mu && !h->cfg.mu_varies) return LBEM_EINVAL;
-    // largest w0/c_L^2 = D eps mu/(1-w0_vac) - D, for the rest-particle scale
-    double wmax = 0.0;
-    for (int64_t c = 0; c < n; ++c) {
-        const double em = eps_r[c] * (mu_r ? mu_r[c] : 1.0);
-        const double v = (double)h->D * em / (1.0 - h->cfg.w0_vac) - (double)h->D;
-        if (std::isfinite(v)) wmax = std::max(wmax, v);
-    }
     double *deps = nullptr, *dmu = nullptr;
     int* dflag = nullptr;
     int flag = 0, rc = LBEM_OK;
@@ -638,14 +621,7 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
     (void)hipFree(dflag);
     h->have_medium = rc == LBEM_OK;
     h->have_fields = false;
-    h->wc0_max = wmax;
     return rc;
-}
-
-static float pow2_at_least(double v)
-{
-    if (!(v > 0.0) || !std::isfinite(v)) return 1.f;
-    return (float)std::ldexp(1.0, (int)std::ceil(std::log2(v)));
 }
 
 int lbem_init_fields(lbem_t h, const double* E, const double* B)
@@ -653,22 +629,11 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B)
     if (!h || !E || !B) return LBEM_EINVAL;
     if (!h->have_medium) return LBEM_ESTATE;
     const int64_t n = h->n;
-    double amax = 0.0;
-    for (int64_t k = 0; k < 3 * n; ++k) {
+    for (int64_t k = 0; k < 3 * n; ++k)
         if (!std::isfinite(E[k]) || !std::isfinite(B[k])) return LBEM_EINVAL;
-        amax = std::max(amax, std::max(std::fabs(E[k]), std::fabs(B[k])));
-    }
     if (h->D == 2) {
         for (int64_t c = 0; c < n; ++c)
             if (E[c] != 0.0 || E[n + c] != 0.0 || B[2 * n + c] != 0.0) return LBEM_EINVAL;
-    }
-    // power-of-two scales per velocity: populations are bounded by the field
-    // magnitude times w_i/c^2 (1/2 moving; the rest scale is further
-    // multiplied in the kernels by the local w0/c^2)
-    const double A = amax > 0.0 ? amax : h->dev_field_scale;
-    for (int i = 0; i < 7; ++i) {
-        h->sc.s[i] = pow2_at_least(i == 0 ? A : 0.5 * A);
-        h->sc.inv[i] = 1.f / h->sc.s[i];
     }
     double *dE = nullptr, *dB = nullptr;
     if (hipMalloc((void**)&dE, 3 * n * 8) != hipSuccess) return LBEM_ENOMEM;
@@ -1023,7 +988,6 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         g.nblocks = g.tiles_x * g.tiles_y * g.nz;
         g.xcd = 0;
         g.strip = 0;
-        G.sc = h->sc;
         G.omega = 1.0 / h->cfg.tau;
         G.tau_half = h->cfg.tau == 0.5;
         G.cur0 = h->cur;

@@ -77,3 +77,32 @@ def random_problem(dim, shape, seed, mu=False, src=True, nsteps=64):
         p.src_comp = comp
         p.amp = rng.standard_normal(nsteps)
     return p
+
+
+def window_problem(p, centre, k):
+    """Periodic window of half-width k+1 around `centre` (x, y[, z])."""
+    dim = p.dim
+    nx, ny, nz = p.shape
+    h = k + 1
+    w = 2 * h + 1
+    ranges = [(np.arange(-h, h + 1) + centre[a]) % p.shape[a] for a in range(dim)]
+    if dim == 2:
+        Y, X = np.meshgrid(ranges[1], ranges[0], indexing="ij")
+        idx = (X + nx * Y).ravel()
+        wshape = (w, w, 1)
+    else:
+        Z, Y, X = np.meshgrid(ranges[2], ranges[1], ranges[0], indexing="ij")
+        idx = (X + nx * (Y + ny * Z)).ravel()
+        wshape = (w, w, w)
+    pos = {int(c): j for j, c in enumerate(idx)}
+    cells, wts = [], []
+    for c, wt in zip(p.src_cells, p.src_weights):
+        j = pos.get(int(c))
+        if j is not None:
+            cells.append(j)
+            wts.append(wt)
+    q = inputs.Problem(dim=dim, shape=wshape, eps_r=p.eps_r[idx], mu_r=None, E0=p.E0[:, idx],
+                       B0=p.B0[:, idx], src_comp=p.src_comp, src_cells=np.asarray(cells, np.int64),
+                       src_weights=np.asarray(wts), amp=p.amp, w0_vac=p.w0_vac)
+    centre_index = h + w * (h + (w * h if dim == 3 else 0))
+    return q, centre_index

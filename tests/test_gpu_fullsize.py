@@ -1,0 +1,70 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times, on sampled outputs.
+
+After k steps a cell's populations depend only on cells within k lattice
+steps (one cell per step along the axes).  So the oracle can compute the
+fields at a sample cell exactly on a periodic window of half-width k+1 cut
+from the full-size medium and source, around that cell: the window's own
+periodic wrap lies outside the sample's dependence cone.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, window_problem
+from oracle import oracle as O
+from paper_1108_2651_amd import inputs, lbem
+
+pytestmark = pytest.mark.gpu
+
+
+def sampled_parity(p, prec, k, samples, tol, streaming="auto"):
+    s = lbem.Solver(p.dim, p.shape, prec, w0_vac=p.w0_vac, streaming=streaming)
+    s.setup(p)
+    s.step(k, p.amp[:k])
+    Eg, Bg = s.moments()
+    s.close()
+    nx, ny, nz = p.shape
+    worst = 0.0
+    for centre in samples:
+        q, ci = window_problem(p, centre, k)
+        o = O.Oracle(q.dim, q.shape, q.tau, q.w0_vac)
+        o.set_medium(q.eps_r)
+        o.init_fields(q.E0, q.B0)
+        if len(q.src_cells):
+            o.set_source(q.src_comp, q.src_cells, q.src_weights)
+        o.step(k, q.amp[:k] if len(q.src_cells) else None)
+        Eo, Bo = o.fields()
+        c = centre[0] + nx * (centre[1] + (ny * centre[2] if p.dim == 3 else 0))
+        scale = max(np.abs(Eo).max(), np.abs(Bo).max(), 1e-30)
+        err = max(np.abs(Eg[:, c] - Eo[:, ci]).max(), np.abs(Bg[:, c] - Bo[:, ci]).max()) / scale
+        announce(f"  sample {tuple(int(v) for v in centre)}: max abs diff / window field scale = {err:.2e}")
+        worst = max(worst, err)
+    assert worst <= tol, worst
+
+
+def test_config2_full_2048_fp32_fused():
+    """The benchmark's primary workload and launch configuration (2048^2
+    FP32, two time steps per launch), 64 steps, 6 sampled cells including
+    the source line and the periodic seams."""
+    k = 64
+    p = inputs.config2(nsteps=k)
+    announce("config2 2048^2 fp32 full size")
+    samples = [(64, 1000), (65, 0), (0, 2047), (700, 1234), (2047, 5), (40, 300)]
+    sampled_parity(p, "f32", k, samples, 1e-5)
+
+
+def test_config3_full_256_fp32_aa():
+    k = 24
+    p = inputs.config3(nsteps=k)
+    announce("config3 256^3 fp32 AA full size")
+    samples = [(128, 128, 128), (130, 125, 131), (0, 0, 255), (200, 17, 90)]
+    sampled_parity(p, "f32", k, samples, 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f16dev"])
+def test_config4_full_512_deviation_storage(prec):
+    k = 16
+    p = inputs.config4(nsteps=k)
+    announce("config4 512^3 f16dev full size")
+    samples = [(256, 256, 256), (255, 258, 250), (511, 0, 300)]
+    sampled_parity(p, prec, k, samples, 2e-3)

@@ -275,6 +275,41 @@ def test_paper_divb_error_second_order():
     assert all(1.7 < q < 2.4 for q in orders), (errs, orders)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_light_cone_window(dim):
+    """After k steps a cell depends only on cells within k steps: the oracle on
+    a periodic window of half-width k+1 reproduces the full lattice at the
+    window's centre (the basis of the full-size sampled GPU checks)."""
+    from gpu_util import window_problem
+    k = 12 if dim == 2 else 6
+    if dim == 2:
+        p = inputs.config2(nsteps=k, n=96)
+        samples = [(64, 50), (0, 95), (30, 3)]
+    else:
+        p = inputs.config3(nsteps=k, crop_n=24)
+        samples = [(12, 12, 12), (0, 23, 5)]
+    full = O.Oracle(p.dim, p.shape, p.tau, p.w0_vac)
+    full.set_medium(p.eps_r)
+    full.init_fields(p.E0, p.B0)
+    full.set_source(p.src_comp, p.src_cells, p.src_weights)
+    full.step(k, p.amp)
+    Ef, Bf = full.fields()
+    nx, ny, nz = p.shape
+    for c in samples:
+        q, ci = window_problem(p, c, k)
+        o = O.Oracle(q.dim, q.shape, q.tau, q.w0_vac)
+        o.set_medium(q.eps_r)
+        o.init_fields(q.E0, q.B0)
+        if len(q.src_cells):
+            o.set_source(q.src_comp, q.src_cells, q.src_weights)
+        o.step(k, q.amp)
+        Ew, Bw = o.fields()
+        cell = c[0] + nx * (c[1] + (ny * c[2] if dim == 3 else 0))
+        scale = max(np.abs(Ef).max(), np.abs(Bf).max())
+        assert np.abs(Ew[:, ci] - Ef[:, cell]).max() < 1e-13 * scale
+        assert np.abs(Bw[:, ci] - Bf[:, cell]).max() < 1e-13 * scale
+
+
 def test_energy_bounded_c1():
     p = inputs.config1(nsteps=500)
     o = run(p, 0)
