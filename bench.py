@@ -32,9 +32,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 2D plain formats advance this many steps per launch (temporal blocking)
-STEPS_PER_LAUNCH_2D = 2
-os.environ.setdefault("LBEM_FUSE", str(STEPS_PER_LAUNCH_2D))
 
 
 def bytes_per_cell(dim: int, prec: str) -> int:
@@ -103,6 +100,7 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
         amp = I.ricker(warmup + steps, 1.0 / 80.0)
     s = lbem.Solver(p.dim, p.shape, prec, tau=p.tau, w0_vac=p.w0_vac, streaming=streaming)
     s.setup(p)
+    spl = s.steps_per_launch
     stream = torch.cuda.current_stream()
     s.step(warmup, amp[:warmup])
     torch.cuda.synchronize()
@@ -119,7 +117,6 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
     n = p.n
     bpc = bytes_per_cell(p.dim, prec)
     st = streaming if streaming != "auto" else ("aa" if (p.dim == 3 and prec in ("f32", "f64")) else "pull")
-    spl = int(os.environ.get("LBEM_FUSE", "1")) if (p.dim == 2 and prec in ("f32", "f64") and st == "pull") else 1
     bpu = bpc / max(spl, 1)        # HBM bytes per cell update when spl steps share one pass
     mlups = n * steps / (ms * 1e-3) / 1e6
     gbs = bpu * n * steps / (ms * 1e-3) / 1e9
@@ -257,8 +254,8 @@ def main():
         cpu = cpu_baseline(p)
 
     # one fused launch reads and writes the state once (and c_L^2 once) for
-    # STEPS_PER_LAUNCH_2D cell updates: 44 B per cell per launch
-    spl = int(os.environ.get("LBEM_FUSE", STEPS_PER_LAUNCH_2D))
+    # spl cell updates: 44 B per cell per launch
+    spl = prim["steps_per_launch"]
     launch_us = prim["avg_launch_us"] * spl
     achieved = prim["bytes_per_cell"] * p.n / (launch_us * 1e-6) / 1e9
     out = {
@@ -279,7 +276,8 @@ def main():
                    "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("c2_2048_f32"),
-                     "kernel": f"k_step_fused2d<float,{spl},8> ({spl} time steps per launch)",
+                     "kernel": (f"k_step_fused2d<float,{spl},8> ({spl} time steps per launch)" if spl > 1
+                                else "k_step_plain<2,float,R_PULL,W_LOCAL,1,false>"),
                      "steps_per_launch": spl, "avg_launch_us": launch_us,
                      "bytes_per_cell_per_launch": prim["bytes_per_cell"], "cells_per_launch": p.n,
                      "bytes_per_cell_update": prim["bytes_per_cell"] / spl,

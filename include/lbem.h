@@ -138,6 +138,11 @@ int lbem_energy(lbem_t h, double out[4]);
 /* Completed steps since lbem_init_fields (-1 for an invalid handle). */
 int64_t lbem_time(lbem_t h);
 
+/* Time steps advanced per kernel launch by lbem_step on this handle (1, or 2-4
+ * when the 2D plain formats fuse several steps into one pass through an LDS
+ * tile; the result is identical to single steps).  EINVAL for NULL. */
+int lbem_steps_per_launch(lbem_t h);
+
 /* Static description of a status code. */
 const char* lbem_strerror(int code);
 

@@ -194,11 +194,14 @@ __device__ __forceinline__ void collide(const T (&f)[Lat<D>::Q][Lat<D>::P], T cl
     for (int p = 0; p < P; ++p) Lam[p] = cl2 * rho[p];
 #pragma unroll
     for (int b = 0; b < D; ++b) Bb[b] = D == 2 ? K[b] : T(0.5) * K[b];
-    const T w0 = T(1) - T(D) * cl2;
     const T wc0 = any_src ? (T(1) / cl2 - T(D)) : T(0);  // w0/c^2 of the rest particle
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const T geq = w0 * rho[p];
+        // rest equilibrium w0 rho written as the remainder rho - D Lambda (the
+        // moving ones carry D Lambda): equal in exact arithmetic (relate.1), but
+        // w0 rounded once per cell would bias the mass of every collision by
+        // the same factor and make the error grow linearly in time
+        const T geq = rho[p] - T(D) * Lam[p];
         T o = tau_half ? (geq + geq) - f[0][p] : f[0][p] + omega * (geq - f[0][p]);
         if (any_src) o -= wc0 * Sp[p];
         out[0][p] = o;
@@ -369,8 +372,46 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         }
     }
 
+    // step 1 over the whole frame: every thread first issues the HBM loads of
+    // all its frame cells, then collides them into LDS layer 0
+    {
+        constexpr int C0 = (FC + NT - 1) / NT;
+        T fv0[C0][Q][1];
+        T cl0[C0];
 #pragma unroll
-    for (int st = 0; st < NS; ++st) {
+        for (int j = 0; j < C0; ++j) {
+            const int k = threadIdx.x + j * NT;
+            if (k < FC) {
+                const int fx = k % W, fy = k / W;
+                int gx = (x0 + fx) % g.nx, gy = (y0 + fy) % g.ny;
+                if (gx < 0) gx += g.nx;
+                if (gy < 0) gy += g.ny;
+                const Cell C = make_cell(g, gx, gy, 0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) fv0[j][i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
+                cl0[j] = cl2a[C.c];
+            }
+        }
+        const T amp = has_src ? amps.a[0] : T(0);
+#pragma unroll
+        for (int j = 0; j < C0; ++j) {
+            const int k = threadIdx.x + j * NT;
+            if (k < FC) {
+                T rho[1], K[2], Sp[1], o[Q][1];
+                moments<2, T>(fv0[j], rho, K);
+                Sp[0] = has_src ? ls[k] * amp : T(0);
+                collide<2, T>(fv0[j], cl0[j], Sp, has_src, omega, tau_half != 0, rho, K, o);
+                lc[k] = cl0[j];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) lp[0][i][k] = o[i][0];
+            }
+        }
+        __syncthreads();
+    }
+
+    // steps 2..NS from LDS on shrinking regions; the last one writes the tile
+#pragma unroll
+    for (int st = 1; st < NS; ++st) {
         const int r = H - st;               // region = tile grown by r
         const int wr = TXF + 2 * r, hr = TY + 2 * r, off = H - r;
         const T amp = has_src ? amps.a[st] : T(0);
@@ -379,39 +420,22 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
             const int fx = off + k % wr, fy = off + k / wr;
             const int f = fy * W + fx;
             T fv[Q][1];
-            T cl2;
-            int gcell = 0;
-            bool store_global = false;
-            if (st == 0) {
-                int gx = (x0 + fx) % g.nx, gy = (y0 + fy) % g.ny;
-                if (gx < 0) gx += g.nx;
-                if (gy < 0) gy += g.ny;
-                const Cell C = make_cell(g, gx, gy, 0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) fv[i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
-                cl2 = cl2a[C.c];
-                lc[f] = cl2;
-            } else {
-                // pull from the previous layer: x - c_i in frame coordinates
-                fv[0][0] = lp[in][0][f];
-                fv[1][0] = lp[in][1][f - 1];
-                fv[2][0] = lp[in][2][f - W];
-                fv[3][0] = lp[in][3][f + 1];
-                fv[4][0] = lp[in][4][f + W];
-                cl2 = lc[f];
-                if (st == NS - 1) {
-                    const int gx = x0 + fx, gy = y0 + fy;    // inside the tile: no wrap needed
-                    store_global = gx < g.nx && gy < g.ny;
-                    gcell = gx + g.nx * gy;
-                }
-            }
+            // pull from the previous layer: x - c_i in frame coordinates
+            fv[0][0] = lp[in][0][f];
+            fv[1][0] = lp[in][1][f - 1];
+            fv[2][0] = lp[in][2][f - W];
+            fv[3][0] = lp[in][3][f + 1];
+            fv[4][0] = lp[in][4][f + W];
+            const T cl2 = lc[f];
             T rho[1], K[2], Sp[1];
             moments<2, T>(fv, rho, K);
             Sp[0] = has_src ? ls[f] * amp : T(0);
             T o[Q][1];
             collide<2, T>(fv, cl2, Sp, has_src, omega, tau_half != 0, rho, K, o);
             if (st == NS - 1) {
-                if (store_global) {
+                const int gx = x0 + fx, gy = y0 + fy;    // inside the tile: no wrap needed
+                if (gx < g.nx && gy < g.ny) {
+                    const int gcell = gx + g.nx * gy;
 #pragma unroll
                     for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.n + gcell] = o[i][0];
                 }

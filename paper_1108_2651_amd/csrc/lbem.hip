@@ -397,7 +397,11 @@ static void make_geo(lbem_s* h)
 static void make_fused_geo(lbem_s* h)
 {
     const bool f64 = h->prec == LBEM_F64;
-    h->fuse_ns = env_int("LBEM_FUSE", 2);
+    // Two steps per pass while the double-buffered state fits the 256 MB
+    // Infinity Cache; beyond it (HBM-bound) four steps halve the traffic again.
+    const double state = (double)h->n * (f64 ? 88.0 : 44.0);
+    const bool big = !f64 && state > 256.0 * 1024 * 1024;
+    h->fuse_ns = env_int("LBEM_FUSE", big ? 4 : 2);
     h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : 8);
     // only the instantiated (steps, rows) pairs; anything else runs single steps
     const int ns = h->fuse_ns, ty = h->fuse_ty;
@@ -812,6 +816,12 @@ int lbem_energy(lbem_t h, double out[4])
 }
 
 int64_t lbem_time(lbem_t h) { return h ? h->t : -1; }
+
+int lbem_steps_per_launch(lbem_t h)
+{
+    if (!h) return LBEM_EINVAL;
+    return fused_ok(h) ? h->fuse_ns : 1;
+}
 
 }  // extern "C"
 

@@ -23,7 +23,8 @@ STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 # every entry point of include/lbem.h
 SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_medium",
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
-           "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy")
+           "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
+           "lbem_steps_per_launch")
 
 
 class Config(C.Structure):
@@ -64,6 +65,7 @@ def load():
     L.lbem_energy.argtypes = [vp, dp]
     L.lbem_time.argtypes = [vp]
     L.lbem_time.restype = i64
+    L.lbem_steps_per_launch.argtypes = [vp]
     L.lbem_strerror.argtypes = [C.c_int]
     L.lbem_strerror.restype = C.c_char_p
     _lib = L
@@ -212,3 +214,7 @@ class Solver:
     @property
     def t(self) -> int:
         return int(load().lbem_time(self._h))
+
+    @property
+    def steps_per_launch(self) -> int:
+        return int(load().lbem_steps_per_launch(self._h))
