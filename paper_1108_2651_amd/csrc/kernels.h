@@ -609,6 +609,133 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
 }
 
 // ---------------------------------------------------------------------------
+// 3D deviation storage, z-marching: neighbour moments staged in LDS
+// ---------------------------------------------------------------------------
+// A block owns a TXD x TYD column tile and a chunk of `lz` planes.  The FP32
+// moments of planes z-1, z, z+1 (tile plus a one-cell halo, periodic) and the
+// per-cell deviation scale sit in a rolling three-plane LDS window; the
+// 16-bit deviations are read once from HBM.  The reconstruction uses the same
+// formulas as dev_load, so the result equals k_step_dev bit for bit.
+constexpr int TXD = 64, TYD = 4;
+
+template <typename H, int RM, bool MU>
+__global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Din, float* Mout, H* Dout,
+                                                  const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                                  const Geo g, const int lz, const SrcArgs<float> s,
+                                                  const float omega, const int tau_half)
+{
+    constexpr int D = 3, Q = 7, P = 3, NM = P + D;
+    constexpr int W = TXD + 2, HH = TYD + 2, PC = W * HH;
+    __shared__ float lm[3][NM][PC];
+    __shared__ float lsc[3][PC];
+    __shared__ float lsrc[P * NT];
+
+    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tx = b % g.tiles_x, r = b / g.tiles_x;
+    const int ty = r % g.tiles_y, zc = r / g.tiles_y;
+    const int x0 = tx * TXD, y0 = ty * TYD, z0 = zc * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const int lx = threadIdx.x % TXD, ly = threadIdx.x / TXD;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool active = x < g.nx && y < g.ny;
+    const int hc = (ly + 1) * W + (lx + 1);
+
+    // source entries of this block, sorted by local index (plane * NT + thread)
+    int s0 = 0, s1 = 0;
+    if (s.off) {
+        s0 = s.off[b];
+        s1 = s.off[b + 1];
+    }
+    const bool has_src = s1 > s0;
+    const bool any_src = has_src || MU;
+
+    auto load_plane = [&](int zz, int q) {
+        zz %= g.nz;
+        if (zz < 0) zz += g.nz;
+        for (int k = threadIdx.x; k < PC; k += NT) {
+            const int hx = k % W, hy = k / W;
+            int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
+            if (gx < 0) gx += g.nx;
+            if (gy < 0) gy += g.ny;
+            const int c = gx + g.nx * (gy + g.ny * zz);
+            float m = 0.f;
+#pragma unroll
+            for (int t = 0; t < NM; ++t) {
+                const float v = Min[(int64_t)t * g.n + c];
+                lm[q][t][k] = v;
+                m = fmaxf(m, fabsf(v));
+            }
+            float sv, iv;
+            pow2_scale(m, sv, iv);
+            lsc[q][k] = sv;
+        }
+    };
+
+    load_plane(z0 - 1, 0);
+    load_plane(z0, 1);
+    for (int z = z0; z < z1; ++z) {
+        const int rel = z - z0;
+        const int qm = rel % 3, qc = (rel + 1) % 3, qp = (rel + 2) % 3;
+        load_plane(z + 1, qp);
+        if (has_src) {
+            for (int k = threadIdx.x; k < P * NT; k += NT) lsrc[k] = 0.f;
+            __syncthreads();
+            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+                const int2 e = s.ent[k];
+                if (e.x / NT == rel) lsrc[e.y * NT + e.x % NT] = s.val[k] * s.amp;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const Cell C = make_cell(g, x, y, z);
+            const float cl2 = cl2a[C.c];
+            const float wc0 = 1.f / cl2 - float(D);
+            float f[Q][P];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                // source cell of population i in the LDS window
+                const int ci_x = RM == R_LOCAL ? 0 : cvel(D, i, 0);
+                const int ci_y = RM == R_LOCAL ? 0 : cvel(D, i, 1);
+                const int ci_z = RM == R_LOCAL ? 0 : cvel(D, i, 2);
+                const int q = ci_z > 0 ? qm : (ci_z < 0 ? qp : qc);
+                const int hi = hc - ci_x - ci_y * W;
+                const int cs = read_cell<D, RM>(C, i);
+                const float sc = lsc[q][hi];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    float Lam[P], Bb[D];
+#pragma unroll
+                    for (int t = 0; t < P; ++t) Lam[t] = (t == p) ? lm[q][t][hi] : 0.f;
+                    const int a = pair_a(D, p), bq = pair_b(D, p);
+#pragma unroll
+                    for (int e = 0; e < D; ++e) {
+                        const bool need = i != 0 && ((e == bq && cvel(D, i, a) != 0) || (e == a && cvel(D, i, bq) != 0));
+                        Bb[e] = need ? lm[q][P + e][hi] : 0.f;
+                    }
+                    const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0);
+                    const float si = i == 0 ? sc * wc0 : 0.5f * sc;
+                    f[i][p] = g0 + si * h2f<H>(Din[(int64_t)(i * P + p) * g.n + cs]);
+                }
+            }
+            float rho[P], K[D], Sp[P];
+            moments<D, float>(f, rho, K);
+#pragma unroll
+            for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[p * NT + threadIdx.x] : 0.f;
+            if (MU) {
+                float dl[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
+                add_mu_source<D, float>(K, cl2, dl, Sp);
+            }
+            float out[Q][P];
+            collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+            dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batched persistent stream-collide: many independent lattices per launch
 // ---------------------------------------------------------------------------
 // One descriptor per resident lattice.  Work items are (lattice, tile) pairs

@@ -118,6 +118,13 @@ struct lbem_s {
     int2* fsrc_ent;
     void* fsrc_val;
     int64_t nfsrc;
+    // 3D deviation kernel marching along z (column tiles x z-chunks)
+    int zmarch, zlz;
+    Geo zgeo;
+    int* zsrc_off;
+    int2* zsrc_ent;
+    void* zsrc_val;
+    int64_t nzsrc;
     // state
     int64_t t;
     bool have_medium, have_fields;
@@ -303,6 +310,19 @@ struct DevImpl : Impl {
     static hipError_t go(lbem_s* h, int from, int to, float amp)
     {
         SrcArgs<float> s;
+        if constexpr (D == 3) {
+            if (h->zmarch) {
+                s.off = h->nzsrc ? h->zsrc_off : nullptr;
+                s.ent = h->zsrc_ent;
+                s.val = (const float*)h->zsrc_val;
+                s.amp = amp;
+                hipLaunchKernelGGL((k_step_dev3z<H, RM, MU>), dim3(h->zgeo.nblocks), dim3(NT), 0, h->stream,
+                                   M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                                   (const float*)h->dlnmu, h->zgeo, h->zlz, s, (float)(1.0 / h->cfg.tau),
+                                   (int)(h->cfg.tau == 0.5));
+                return hipGetLastError();
+            }
+        }
         s.off = h->nsrc ? h->src_off : nullptr;
         s.ent = h->src_ent;
         s.val = (const float*)h->src_val;
@@ -417,6 +437,20 @@ static void make_fused_geo(lbem_s* h)
     g.strip = 0;
 }
 
+static void make_zmarch_geo(lbem_s* h)
+{
+    h->zmarch = (h->D == 3 && h->prec >= LBEM_F16DEV) ? env_int("LBEM_DEV3Z", 1) : 0;
+    h->zlz = std::max(1, env_int("LBEM_DEV3Z_LZ", 16));
+    Geo& g = h->zgeo;
+    g = h->geo;
+    g.tiles_x = (g.nx + TXD - 1) / TXD;
+    g.tiles_y = (g.ny + TYD - 1) / TYD;
+    const int nzc = (g.nz + h->zlz - 1) / h->zlz;
+    g.nblocks = g.tiles_x * g.tiles_y * nzc;
+    g.strip = 0;
+    g.xcd = env_int("LBEM_DEV3Z_XCD", 0);
+}
+
 // inverse of tile_coords()
 static int tile_id(const Geo& g, int tx, int ty, int z)
 {
@@ -502,6 +536,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     if (cfg->mu_varies) h->vec = 1;
     make_geo(h);
     make_fused_geo(h);
+    make_zmarch_geo(h);
     h->impl = make_impl(h->D, h->prec);
     if (h->impl && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
         delete h->impl;
@@ -526,9 +561,55 @@ static void free_source(lbem_s* h)
     if (h->fsrc_ent) (void)hipFree(h->fsrc_ent);
     if (h->fsrc_val) (void)hipFree(h->fsrc_val);
     h->src_off = nullptr; h->src_ent = nullptr; h->src_val = nullptr;
+    if (h->zsrc_off) (void)hipFree(h->zsrc_off);
+    if (h->zsrc_ent) (void)hipFree(h->zsrc_ent);
+    if (h->zsrc_val) (void)hipFree(h->zsrc_val);
     h->fsrc_off = nullptr; h->fsrc_ent = nullptr; h->fsrc_val = nullptr;
+    h->zsrc_off = nullptr; h->zsrc_ent = nullptr; h->zsrc_val = nullptr;
     h->nsrc = 0;
     h->nfsrc = 0;
+    h->nzsrc = 0;
+}
+
+// Per-block source entries of the z-marching 3D tiling: local index
+// (plane within the chunk) * NT + thread, pair, value.
+static int build_zmarch_source(lbem_s* h, const std::vector<std::pair<int64_t, double>>& cells, int pp)
+{
+    const Geo& g = h->zgeo;
+    struct Item { int b, local; float v; };
+    std::vector<Item> items;
+    items.reserve(cells.size());
+    for (auto& e : cells) {
+        const int c = (int)e.first;
+        const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
+        const int tx = x / TXD, ty = y / TYD, zc = z / h->zlz;
+        const int b = (zc * g.tiles_y + ty) * g.tiles_x + tx;
+        const int local = (z - zc * h->zlz) * NT + (y - ty * TYD) * TXD + (x - tx * TXD);
+        items.push_back({b, local, (float)e.second});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b2) {
+        return a.b != b2.b ? a.b < b2.b : a.local < b2.local;
+    });
+    std::vector<int> off(g.nblocks + 1, 0);
+    for (auto& it : items) off[it.b + 1]++;
+    for (int b = 0; b < g.nblocks; ++b) off[b + 1] += off[b];
+    std::vector<int2> ent(items.size());
+    std::vector<float> val(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        ent[k] = make_int2(items[k].local, pp);
+        val[k] = items[k].v;
+    }
+    const size_t ms = items.size();
+    if (hipMalloc((void**)&h->zsrc_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->zsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->zsrc_val, std::max<size_t>(ms, 1) * sizeof(float)) != hipSuccess)
+        return LBEM_ENOMEM;
+    hipError_t e = hipMemcpy(h->zsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->zsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->zsrc_val, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->nzsrc = (int64_t)ms;
+    return LBEM_OK;
 }
 
 // Per-tile source entries of the fused 2D tiling: every frame cell (tile plus
@@ -742,6 +823,12 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     }
     if (e != hipSuccess) { free_source(h); return LBEM_EDEVICE; }
     h->nsrc = (int64_t)ms;
+    if (h->zmarch) {
+        std::vector<std::pair<int64_t, double>> cv(merged.size());
+        for (size_t k = 0; k < merged.size(); ++k) cv[k] = {merged[k].first, src_value[k]};
+        const int rc = build_zmarch_source(h, cv, pp);
+        if (rc != LBEM_OK) { free_source(h); return rc; }
+    }
     if (D == 2 && h->prec <= LBEM_F32 && h->fuse_ns > 1) {
         std::vector<double> dense((size_t)n, 0.0);
         for (size_t k = 0; k < merged.size(); ++k) dense[(size_t)merged[k].first] = src_value[k];

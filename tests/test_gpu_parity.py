@@ -167,11 +167,26 @@ def test_deviation_tile_orders_bitwise(prec):
     """Strip / row-major tile orders and XCD remapping of the deviation kernel
     give identical results, with a source spread over many tiles."""
     p = random_problem(3, (64, 48, 10), seed=95, nsteps=30)
-    ref = gpu_run(p, 30, prec, env={"LBEM_STRIP": 0}).moments()
-    for env in ({"LBEM_STRIP": 4}, {"LBEM_STRIP": 2, "LBEM_XCD": 0}, {"LBEM_VEC": 2, "LBEM_STRIP": 3}):
+    ref = gpu_run(p, 30, prec, env={"LBEM_STRIP": 0, "LBEM_DEV3Z": 0}).moments()
+    for env in ({"LBEM_STRIP": 4, "LBEM_DEV3Z": 0}, {"LBEM_STRIP": 2, "LBEM_XCD": 0, "LBEM_DEV3Z": 0},
+                {"LBEM_VEC": 2, "LBEM_STRIP": 3, "LBEM_DEV3Z": 0}, {"LBEM_DEV3Z": 1},
+                {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 3, "LBEM_DEV3Z_XCD": 0}, {"LBEM_DEV3Z_LZ": 1}):
         announce(f"dev tile order {prec} {env}")
         got = gpu_run(p, 30, prec, env=env).moments()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
+
+
+@pytest.mark.parametrize("shape,mu", [((19, 13, 11), True), ((70, 5, 9), False), ((130, 9, 3), False)])
+def test_deviation_zmarch_ragged_bitwise(shape, mu):
+    """The z-marching 3D deviation kernel equals the per-cell gather kernel on
+    ragged boxes (tiles wider than the box, chunks longer than nz, mu term)."""
+    p = random_problem(3, shape, seed=sum(shape), mu=mu, nsteps=21)
+    for prec in ("f16dev", "bf16dev"):
+        ref = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 0}).moments()
+        for lz in (16, 4):
+            announce(f"zmarch {shape} mu={mu} {prec} lz={lz}")
+            got = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": lz}).moments()
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (prec, lz)
 
 
 def test_moments_on_device():
