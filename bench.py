@@ -116,7 +116,7 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
     diag = s.energy(check=False)
     n = p.n
     bpc = bytes_per_cell(p.dim, prec)
-    st = streaming if streaming != "auto" else ("aa" if (p.dim == 3 and prec in ("f32", "f64")) else "pull")
+    st = streaming if streaming != "auto" else "pull"
     bpu = bpc / max(spl, 1)        # HBM bytes per cell update when spl steps share one pass
     mlups = n * steps / (ms * 1e-3) / 1e6
     gbs = bpu * n * steps / (ms * 1e-3) / 1e9
@@ -219,9 +219,9 @@ def main():
     if not args.no_variants:
         plan = [("c2", "f32", "aa", 2000, 20), ("2d8192", "f32", "pull", 200, 10),
                 ("2d8192", "f32", "aa", 200, 10), ("2d8192", "f16dev", "pull", 200, 10),
-                ("c3", "f32", "aa", 200, 10), ("c3", "f32", "pull", 200, 10),
+                ("c3", "f32", "pull", 200, 10), ("c3", "f32", "aa", 200, 10),
                 ("c3", "f16dev", "pull", 200, 10), ("c3", "bf16dev", "pull", 200, 10),
-                ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5)]
+                ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5)]
         plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
         for name, prec, st, k, w in plan:
             print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)

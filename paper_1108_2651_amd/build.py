@@ -18,6 +18,10 @@ FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 (v_pk_*_f32) instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit a*b+c -> fma contraction: every kernel then rounds the shared
+    # per-cell update identically (fused, batched and single-step results agree
+    # bit for bit), and the bandwidth-bound kernels do not need the fused ops
+    "-ffp-contract=off",
     "-Wno-unused-result",
 ]
 

@@ -449,6 +449,133 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 }
 
 // ---------------------------------------------------------------------------
+// 3D temporal blocking: two time steps per launch, marching along z
+// ---------------------------------------------------------------------------
+// A block owns a TX x TY column tile and a chunk of lz planes.  For every
+// plane zz from z0-1 to z0+lz it runs step 1 on the tile grown by one cell in
+// x and y (pulling the stored state from HBM), keeping in LDS the in-plane
+// components (rest, +-x, +-y: with the halo) and, for tile cells only, the +z
+// components (ring of 3 planes) and -z components (one plane); then it runs
+// step 2 on plane zz-1 of the tile, pulling from LDS, and writes it.  Every
+// update is the same collide() as the single-step kernel: bit-identical.
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
+                                                    const Geo g, const int lz, const FusedSrc<T> fs,
+                                                    const AmpPack<T, 2> amps, const T omega, const int tau_half)
+{
+    constexpr int D = 3, Q = 7, P = 3;
+    constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;
+    static_assert(TC == NT, "one tile cell per thread");
+    constexpr int NIP = 5;                       // in-plane velocities 0, +x, +y, -x, -y
+    __shared__ T lin[2][NIP * P][FC];
+    __shared__ T lpz[3][P][TC];
+    __shared__ T lmz[P][TC];
+    __shared__ T lsrc[2][P][FC];
+
+    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tx = b % g.tiles_x, r = b / g.tiles_x;
+    const int ty = r % g.tiles_y, zc = r / g.tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = zc * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int hc = (ly + 1) * W + (lx + 1);
+
+    int s0 = 0, s1 = 0;
+    if (fs.off) {
+        s0 = fs.off[b];
+        s1 = fs.off[b + 1];
+    }
+    const bool has_src = s1 > s0;
+
+    // in-plane slot of velocity i (0, +x, +y, -x, -y), -1 for +-z
+    auto ipl = [](int i) { return i == 0 ? 0 : (i == 1 ? 1 : (i == 2 ? 2 : (i == 4 ? 3 : (i == 5 ? 4 : -1)))); };
+
+    for (int zz = z0 - 1; zz <= z1; ++zz) {
+        const int rel = zz - (z0 - 1);          // 0 .. lz+1
+        const int bi = rel & 1;
+        int gz = zz % g.nz;
+        if (gz < 0) gz += g.nz;
+        if (has_src) {
+            for (int k = threadIdx.x; k < P * FC; k += NT) (&lsrc[bi][0][0])[k] = T(0);
+            __syncthreads();
+            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+                const int2 e = fs.ent[k];          // x = plane offset * FC + frame cell, y = pair
+                if (e.x / FC == rel) lsrc[bi][e.y][e.x % FC] = fs.val[k];
+            }
+            __syncthreads();
+        }
+        // ---- step 1 on plane zz, frame cells
+        for (int k = threadIdx.x; k < FC; k += NT) {
+            const int hx = k % W, hy = k / W;
+            int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
+            if (gx < 0) gx += g.nx;
+            if (gy < 0) gy += g.ny;
+            const Cell C = make_cell(g, gx, gy, gz);
+            T f[Q][P];
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int p = 0; p < P; ++p) f[i][p] = src[(int64_t)(i * P + p) * g.n + read_cell<D, R_PULL>(C, i)];
+            const T cl2 = cl2a[C.c];
+            T rho[P], K[D], Sp[P], out[Q][P];
+            moments<D, T>(f, rho, K);
+#pragma unroll
+            for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[bi][p][k] * amps.a[0] : T(0);
+            collide<D, T>(f, cl2, Sp, has_src, omega, tau_half != 0, rho, K, out);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int sl = ipl(i);
+                if (sl >= 0) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) lin[bi][sl * P + p][k] = out[i][p];
+                }
+            }
+            const bool tile = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
+            if (tile) {
+                const int tcell = (hy - 1) * TX + (hx - 1);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    lpz[rel % 3][p][tcell] = out[3][p];
+                    lmz[p][tcell] = out[6][p];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- step 2 on plane zz-1 of the tile
+        const int zc2 = zz - 1;
+        if (zc2 >= z0 && zc2 < z1) {
+            const int x = x0 + lx, y = y0 + ly;
+            if (x < g.nx && y < g.ny) {
+                const int pb = (rel - 1) & 1;       // plane zz-1's in-plane buffer
+                T f[Q][P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    f[0][p] = lin[pb][0 * P + p][hc];
+                    f[1][p] = lin[pb][1 * P + p][hc - 1];
+                    f[2][p] = lin[pb][2 * P + p][hc - W];
+                    f[4][p] = lin[pb][3 * P + p][hc + 1];
+                    f[5][p] = lin[pb][4 * P + p][hc + W];
+                    f[3][p] = lpz[(rel + 1) % 3][p][threadIdx.x];   // plane zz-2, moving +z
+                    f[6][p] = lmz[p][threadIdx.x];                   // plane zz, moving -z
+                }
+                const int c = x + g.nx * (y + g.ny * zc2);
+                const T cl2 = cl2a[c];
+                T rho[P], K[D], Sp[P], out[Q][P];
+                moments<D, T>(f, rho, K);
+#pragma unroll
+                for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[pb][p][hc] * amps.a[1] : T(0);
+                collide<D, T>(f, cl2, Sp, has_src, omega, tau_half != 0, rho, K, out);
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) dst[(int64_t)(i * P + p) * g.n + c] = out[i][p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // deviation storage: FP32 moments + 16-bit scaled deviations, FP32 arithmetic
 // ---------------------------------------------------------------------------
 template <typename H>

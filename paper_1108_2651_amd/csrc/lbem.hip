@@ -54,8 +54,9 @@ bool valid_cfg(const lbem_config* c)
 
 int resolve_streaming(const lbem_config* c)
 {
+    // pull by default: the fused multi-step kernels need the second copy;
+    // the in-place AA pattern (half the memory) is available on request
     if (c->streaming != LBEM_STREAM_AUTO) return c->streaming;
-    if (c->prec <= LBEM_F32 && c->dim == 3) return LBEM_STREAM_AA;
     return LBEM_STREAM_PULL;
 }
 
@@ -111,8 +112,10 @@ struct lbem_s {
     // tiling of the step kernels
     Geo geo;
     int vec;
-    // 2D temporal blocking (fuse_ns steps per launch; 1 = off)
+    // temporal blocking (fuse_ns steps per launch; 1 = off): 2D tiles 64 x fuse_ty,
+    // 3D column tiles f3_tx x f3_ty marching over chunks of f3_lz planes
     int fuse_ns, fuse_ty;
+    int f3_tx, f3_ty, f3_lz;
     Geo fgeo;
     int* fsrc_off;
     int2* fsrc_ent;
@@ -211,9 +214,31 @@ static hipError_t go_fused(lbem_s* h, const T* src, T* dst, const double* amp)
     return hipErrorInvalidValue;
 }
 
+template <typename T, int TX, int TY>
+static hipError_t go_fused3_t(lbem_s* h, const T* src, T* dst, const double* amp)
+{
+    FusedSrc<T> fs;
+    fs.off = h->nfsrc ? h->fsrc_off : nullptr;
+    fs.ent = h->fsrc_ent;
+    fs.val = (const T*)h->fsrc_val;
+    AmpPack<T, 2> a;
+    for (int j = 0; j < 2; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
+    hipLaunchKernelGGL((k_step_fused3d<T, TX, TY>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src, dst,
+                       (const T*)h->cl2, h->fgeo, h->f3_lz, fs, a, (T)(1.0 / h->cfg.tau),
+                       (int)(h->cfg.tau == 0.5));
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t go_fused3(lbem_s* h, const T* src, T* dst, const double* amp)
+{
+    if (h->f3_tx == 64) return go_fused3_t<T, 64, 4>(h, src, dst, amp);
+    return go_fused3_t<T, 32, 8>(h, src, dst, amp);
+}
+
 static bool fused_ok(const lbem_s* h)
 {
-    return h->D == 2 && h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && !h->mu_set && h->fuse_ns > 1;
+    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && !h->mu_set && h->fuse_ns > 1;
 }
 
 template <int D, typename T>
@@ -267,14 +292,13 @@ struct PlainImpl : Impl {
     }
     hipError_t step_fused(lbem_s* h, const double* amp) override
     {
-        if constexpr (D == 2) {
-            const T* a = (const T*)h->pop[h->cur];
-            T* b = (T*)h->pop[1 - h->cur];
-            hipError_t e = go_fused<T>(h, a, b, amp);
-            h->cur = 1 - h->cur;
-            return e;
-        }
-        return hipErrorInvalidValue;
+        const T* a = (const T*)h->pop[h->cur];
+        T* b = (T*)h->pop[1 - h->cur];
+        hipError_t e;
+        if constexpr (D == 2) e = go_fused<T>(h, a, b, amp);
+        else e = go_fused3<T>(h, a, b, amp);
+        h->cur = 1 - h->cur;
+        return e;
     }
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
@@ -414,8 +438,31 @@ static void make_geo(lbem_s* h)
     if (g.strip <= 0 || nz == 1 || g.strip >= g.tiles_y || g.tiles_y % g.strip != 0) g.strip = 0;
 }
 
+static void make_fused3_geo(lbem_s* h)
+{
+    const bool f64 = h->prec == LBEM_F64;
+    // FP64 frames do not fit enough blocks per CU for the pair to pay off
+    // (measured slower than single steps at 256^3), so FP64 runs single steps
+    // unless asked for.
+    h->fuse_ns = env_int("LBEM_FUSE3", f64 ? 1 : 2) == 2 ? 2 : 1;
+    h->f3_tx = env_int("LBEM_FUSE3_TX", f64 ? 32 : 64) == 64 && !f64 ? 64 : 32;
+    h->f3_ty = NT / h->f3_tx;
+    h->f3_lz = std::max(1, env_int("LBEM_FUSE3_LZ", 32));
+    Geo& g = h->fgeo;
+    g = h->geo;
+    g.tiles_x = (g.nx + h->f3_tx - 1) / h->f3_tx;
+    g.tiles_y = (g.ny + h->f3_ty - 1) / h->f3_ty;
+    g.nblocks = g.tiles_x * g.tiles_y * ((g.nz + h->f3_lz - 1) / h->f3_lz);
+    g.strip = 0;
+    g.xcd = env_int("LBEM_FUSE3_XCD", 0);
+}
+
 static void make_fused_geo(lbem_s* h)
 {
+    if (h->D == 3) {
+        make_fused3_geo(h);
+        return;
+    }
     const bool f64 = h->prec == LBEM_F64;
     // Two steps per pass while the double-buffered state fits the 256 MB
     // Infinity Cache; beyond it (HBM-bound) four steps halve the traffic again.
@@ -569,6 +616,60 @@ static void free_source(lbem_s* h)
     h->nsrc = 0;
     h->nfsrc = 0;
     h->nzsrc = 0;
+}
+
+// Per-block source entries of the fused 3D tiling: every (plane offset,
+// frame cell) of the block's z range z0-1 .. z0+lz (periodic images included)
+// that carries a current; entry.x = plane offset * frame cells + frame cell.
+static int build_fused3_source(lbem_s* h, const std::vector<double>& dense, int pp)
+{
+    const Geo& g = h->fgeo;
+    const int TX = h->f3_tx, TY = h->f3_ty, LZ = h->f3_lz;
+    const int W = TX + 2, HH = TY + 2, FC = W * HH;
+    std::vector<int> off(g.nblocks + 1, 0);
+    std::vector<int2> ent;
+    std::vector<double> val;
+    for (int b = 0; b < g.nblocks; ++b) {
+        const int tx = b % g.tiles_x, r = b / g.tiles_x;
+        const int ty = r % g.tiles_y, zc = r / g.tiles_y;
+        const int x0 = tx * TX, y0 = ty * TY, z0 = zc * LZ;
+        for (int po = 0; po < LZ + 2; ++po) {
+            int gz = (z0 - 1 + po) % g.nz;
+            if (gz < 0) gz += g.nz;
+            for (int hy = 0; hy < HH; ++hy) {
+                int gy = (y0 - 1 + hy) % g.ny;
+                if (gy < 0) gy += g.ny;
+                for (int hx = 0; hx < W; ++hx) {
+                    int gx = (x0 - 1 + hx) % g.nx;
+                    if (gx < 0) gx += g.nx;
+                    const double v = dense[(size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz)];
+                    if (v != 0.0) {
+                        ent.push_back(make_int2(po * FC + hy * W + hx, pp));
+                        val.push_back(v);
+                    }
+                }
+            }
+        }
+        off[b + 1] = (int)ent.size();
+    }
+    const size_t ms = ent.size(), tv = h->prec == LBEM_F64 ? 8 : 4;
+    if (hipMalloc((void**)&h->fsrc_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->fsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->fsrc_val, std::max<size_t>(ms, 1) * tv) != hipSuccess)
+        return LBEM_ENOMEM;
+    hipError_t e = hipMemcpy(h->fsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->fsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) {
+        if (tv == 8) {
+            e = hipMemcpy(h->fsrc_val, val.data(), ms * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> f(val.begin(), val.end());
+            e = hipMemcpy(h->fsrc_val, f.data(), ms * 4, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->nfsrc = (int64_t)ms;
+    return LBEM_OK;
 }
 
 // Per-block source entries of the z-marching 3D tiling: local index
@@ -829,10 +930,10 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
         const int rc = build_zmarch_source(h, cv, pp);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
-    if (D == 2 && h->prec <= LBEM_F32 && h->fuse_ns > 1) {
+    if (h->prec <= LBEM_F32 && h->fuse_ns > 1) {
         std::vector<double> dense((size_t)n, 0.0);
         for (size_t k = 0; k < merged.size(); ++k) dense[(size_t)merged[k].first] = src_value[k];
-        const int rc = build_fused_source(h, dense);
+        const int rc = D == 2 ? build_fused_source(h, dense) : build_fused3_source(h, dense, pp);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
     return LBEM_OK;

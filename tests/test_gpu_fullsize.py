@@ -53,12 +53,14 @@ def test_config2_full_2048_fp32_fused():
     sampled_parity(p, "f32", k, samples, 1e-5)
 
 
-def test_config3_full_256_fp32_aa():
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_config3_full_256_fp32(streaming):
+    """Default pull streaming runs two fused steps per launch; AA single steps."""
     k = 24
     p = inputs.config3(nsteps=k)
-    announce("config3 256^3 fp32 AA full size")
+    announce(f"config3 256^3 fp32 {streaming} full size")
     samples = [(128, 128, 128), (130, 125, 131), (0, 0, 255), (200, 17, 90)]
-    sampled_parity(p, "f32", k, samples, 1e-5)
+    sampled_parity(p, "f32", k, samples, 1e-5, streaming=streaming)
 
 
 @pytest.mark.parametrize("prec", ["f16dev"])

@@ -90,6 +90,24 @@ def test_temporal_blocking_bitwise(prec, shape):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (ns, ty)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(40, 24, 20), (70, 9, 5), (33, 17, 37), (5, 3, 7), (128, 4, 2)])
+def test_temporal_blocking_3d_bitwise(prec, shape):
+    """Two fused 3D steps per launch (z-marching, LDS plane rings, sources
+    with periodic images) equal two single steps bit for bit."""
+    p = random_problem(3, shape, seed=sum(shape) + 13, nsteps=31)
+    ref = gpu_run(p, 31, prec, "pull", env={"LBEM_FUSE3": 1}).moments()
+    combos = [dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=32), dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=3),
+              dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=1)]
+    for env in combos:
+        env["LBEM_FUSE3"] = 2
+        announce(f"fused3d {prec} {shape} {env}")
+        s = gpu_run(p, 31, prec, "pull", env=env)
+        assert s.steps_per_launch == 2, env
+        got = s.moments()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
+
+
 def test_tau_not_half():
     p = random_problem(2, (40, 24, 1), seed=3, nsteps=80)
     compare(p, 80, "f64", tau=0.8)
