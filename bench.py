@@ -42,13 +42,14 @@ def bytes_per_cell(dim: int, prec: str) -> int:
         return 2 * Q * P * 8 + 8
     if prec == "f32":
         return 2 * Q * P * 4 + 4
-    return 2 * ((P + dim) * 4 + Q * P * 2) + 4
+    slots = (Q - 1) * P - dim if "ghost" in prec else Q * P
+    return 2 * ((P + dim) * 4 + slots * 2) + 4
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("paper_1108_2651_amd/csrc/kernels.h", "paper_1108_2651_amd/csrc/lattice.h",
-              "paper_1108_2651_amd/csrc/lbem.hip"):
+              "paper_1108_2651_amd/csrc/lbem.hip", "paper_1108_2651_amd/build.py"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -221,7 +222,9 @@ def main():
                 ("2d8192", "f32", "aa", 200, 10), ("2d8192", "f16dev", "pull", 200, 10),
                 ("c3", "f32", "pull", 200, 10), ("c3", "f32", "aa", 200, 10),
                 ("c3", "f16dev", "pull", 200, 10), ("c3", "bf16dev", "pull", 200, 10),
-                ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5)]
+                ("c3", "f16ghost", "pull", 200, 10),
+                ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5),
+                ("c4", "f16ghost", "pull", 50, 5)]
         plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
         for name, prec, st, k, w in plan:
             print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)

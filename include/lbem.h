@@ -57,12 +57,17 @@ typedef enum {
     LBEM_F16DEV = 2,   /* FP32 conserved moments + FP16 deviations from the local
                           equilibrium, scaled by a power of two per velocity;
                           all collision arithmetic in FP32                        */
-    LBEM_BF16DEV = 3   /* as LBEM_F16DEV with BF16 deviations                     */
+    LBEM_BF16DEV = 3,  /* as LBEM_F16DEV with BF16 deviations                     */
+    LBEM_F16GHOST = 4, /* FP32 conserved moments + FP16 ghost coordinates: only the
+                          (Q-1)P - D moving deviations that the zero-moment
+                          constraints leave free are stored (2D 2 of 5, 3D 15 of
+                          21 per cell); the rest follow from the constraints    */
+    LBEM_BF16GHOST = 5 /* as LBEM_F16GHOST with BF16 ghost coordinates           */
 } lbem_prec;
 
 /* Streaming pattern (eq. STREAM) of the stored populations. */
 typedef enum {
-    LBEM_STREAM_AUTO = 0, /* AA for F64/F32 in 3D, pull otherwise                 */
+    LBEM_STREAM_AUTO = 0, /* pull (the multi-step fused kernels need two copies) */
     LBEM_STREAM_PULL = 1, /* two copies; each step gathers from x - c_i           */
     LBEM_STREAM_AA = 2    /* one copy updated in place, alternating even/odd steps
                              (F64/F32 only)                                       */
@@ -167,8 +172,10 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
 
 /* Enqueue one tick on the batch stream: handle k advances by nsteps[k] steps
  * (0 <= nsteps[k] <= steps_per_tick; 0 leaves it untouched).  Members must be
- * distinct, initialised (ESTATE otherwise), created with pull streaming,
- * without a current source and with mu == 1 (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member synchronises.
+ * distinct, initialised (ESTATE otherwise), created with pull streaming in a
+ * format up to LBEM_BF16DEV, without a current source and with mu == 1
+ * (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member
+ * synchronises.
  * The host-side table is double-buffered: a call waits only for the upload of
  * the tick before the previous one. */
 int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count);

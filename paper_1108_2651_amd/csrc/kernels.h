@@ -638,8 +638,87 @@ __device__ __forceinline__ float dev_eq(int i, int p, const float (&Lam)[Lat<D>:
     return 0.5f * twice_eq_moving<D, float>(i, p, Lam[p], Bb);
 }
 
+// Ghost-coordinate encoding.  The deviation n = g' - g0(m(g')) of a cell has
+// vanishing moments: sum_i n_{i,p} = 0 for every pair p, and each component e
+// of the contracted first moment, sum_{i,p} k(i,p,e) n_{i,p} with k below, is
+// zero.  So P + D of the Q P entries follow from the others and only the
+// remaining (Q-1) P - D moving entries are stored.  Dropped: every rest entry
+// (recovered at its own cell from the cell's moving entries) and, for each e,
+// the entry moving along -o in the lowest pair {e, o}; that entry appears in no
+// other constraint, and its own constraint involves no other dropped entry.
+__host__ __device__ constexpr int kcoef(int D, int i, int p, int e)
+{
+    return (e == pair_b(D, p) ? cvel(D, i, pair_a(D, p)) : 0) -
+           (e == pair_a(D, p) ? cvel(D, i, pair_b(D, p)) : 0);
+}
+__host__ __device__ constexpr int ghost_pair(int D, int e) { return D == 2 ? 0 : (e == 2 ? 1 : 0); }
+__host__ __device__ constexpr int ghost_dir(int D, int e)
+{
+    return 1 + D + (pair_a(D, ghost_pair(D, e)) == e ? pair_b(D, ghost_pair(D, e)) : pair_a(D, ghost_pair(D, e)));
+}
+// the first-moment component whose constraint recovers entry (i,p), or -1
+__host__ __device__ constexpr int ghost_dropped_by(int D, int i, int p)
+{
+    for (int e = 0; e < D; ++e)
+        if (ghost_dir(D, e) == i && ghost_pair(D, e) == p) return e;
+    return -1;
+}
+// slot of entry (i,p) in the deviation arrays, -1 if it is not stored
+template <int D, bool GH>
+__host__ __device__ constexpr int dev_slot(int i, int p)
+{
+    constexpr int P = Lat<D>::P;
+    if (!GH) return i * P + p;
+    if (i == 0 || ghost_dropped_by(D, i, p) >= 0) return -1;
+    int s = 0;
+    for (int j = 1; j <= 2 * D; ++j)
+        for (int q = 0; q < P; ++q) {
+            if (j == i && q == p) return s;
+            if (ghost_dropped_by(D, j, q) < 0) ++s;
+        }
+    return -1;
+}
+template <int D, bool GH>
+struct DevSlots {
+    static constexpr int N = GH ? 2 * D * Lat<D>::P - D : Lat<D>::Q * Lat<D>::P;
+};
+
+// scaled code of moving entry (i,p) at cell cs: stored, or recovered from its
+// first-moment constraint
+template <int D, typename H, bool GH>
+__device__ __forceinline__ float dev_code(const H* Dv, int64_t n, int i, int p, int cs)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    const int e = GH ? ghost_dropped_by(D, i, p) : -1;
+    if (e < 0) return h2f<H>(Dv[(int64_t)dev_slot<D, GH>(i, p) * n + cs]);
+    float sum = 0.f;
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int k = kcoef(D, j, q, e);
+            if (k == 0 || (j == i && q == p)) continue;
+            const float v = h2f<H>(Dv[(int64_t)dev_slot<D, GH>(j, q) * n + cs]);
+            sum = k > 0 ? sum + v : sum - v;
+        }
+    return kcoef(D, i, p, e) > 0 ? -sum : sum;
+}
+
+// deviation of population (i,p) stored at cell cs with cell scale s
+template <int D, typename H, bool GH>
+__device__ __forceinline__ float dev_value(const H* Dv, int64_t n, int i, int p, int cs, float s, float wc0)
+{
+    constexpr int Q = Lat<D>::Q;
+    if (!GH) return (i == 0 ? s * wc0 : 0.5f * s) * dev_code<D, H, false>(Dv, n, i, p, cs);
+    if (i != 0) return 0.5f * s * dev_code<D, H, true>(Dv, n, i, p, cs);
+    float sum = 0.f;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) sum += dev_code<D, H, true>(Dv, n, j, p, cs);
+    return -0.5f * s * sum;
+}
+
 // Reconstruct population (i,p) stored at cell cs (moments M, deviations Dv).
-template <int D, typename H>
+template <int D, typename H, bool GH>
 __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n, int i, int p, int cs,
                                           float wc0_here)
 {
@@ -657,13 +736,12 @@ __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n
     const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0_here);
     float s, inv;
     pow2_scale(cell_magnitude<D>(M, n, cs), s, inv);
-    const float si = i == 0 ? s * wc0_here : 0.5f * s;
-    return g0 + si * h2f<H>(Dv[(int64_t)(i * P + p) * n + cs]);
+    return g0 + dev_value<D, H, GH>(Dv, n, i, p, cs, s, wc0_here);
 }
 
 // Encode a post-collision state: its moments (FP32) and the scaled 16-bit
 // deviations from the equilibrium of those moments.
-template <int D, typename H>
+template <int D, typename H, bool GH>
 __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
                                           int64_t n, int c, float* Mout, H* Dout)
 {
@@ -690,12 +768,14 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p) {
+            const int sl = dev_slot<D, GH>(i, p);
+            if (sl < 0) continue;
             const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
-            Dout[(int64_t)(i * P + p) * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
+            Dout[(int64_t)sl * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
         }
 }
 
-template <int D, typename H, int RM, int VEC, bool MU>
+template <int D, typename H, bool GH, int RM, int VEC, bool MU>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
@@ -718,7 +798,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         for (int i = 0; i < Q; ++i)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
+                f[i][p] = dev_load<D, H, GH>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
         float rho[P], K[D], Sp[P];
         moments<D, float>(f, rho, K);
 #pragma unroll
@@ -731,7 +811,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         }
         float out[Q][P];
         collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-        dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+        dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
     }
 }
 
@@ -745,7 +825,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
 // formulas as dev_load, so the result equals k_step_dev bit for bit.
 constexpr int TXD = 64, TYD = 4;
 
-template <typename H, int RM, bool MU>
+template <typename H, bool GH, int RM, bool MU>
 __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Din, float* Mout, H* Dout,
                                                   const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                   const Geo g, const int lz, const SrcArgs<float> s,
@@ -840,8 +920,7 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
                         Bb[e] = need ? lm[q][P + e][hi] : 0.f;
                     }
                     const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0);
-                    const float si = i == 0 ? sc * wc0 : 0.5f * sc;
-                    f[i][p] = g0 + si * h2f<H>(Din[(int64_t)(i * P + p) * g.n + cs]);
+                    f[i][p] = g0 + dev_value<D, H, GH>(Din, g.n, i, p, cs, sc, wc0);
                 }
             }
             float rho[P], K[D], Sp[P];
@@ -856,7 +935,7 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
             }
             float out[Q][P];
             collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-            dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+            dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
         }
         __syncthreads();
     }
@@ -957,14 +1036,15 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int p = 0; p < P; ++p) f[i][p] = dev_load<D, H>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
+        for (int p = 0; p < P; ++p)
+            f[i][p] = dev_load<D, H, false>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
     float rho[P], K[D], Sp[P];
     moments<D, float>(f, rho, K);
 #pragma unroll
     for (int p = 0; p < P; ++p) Sp[p] = 0.f;
     float out[Q][P];
     collide<D, float>(f, cl2, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, out);
-    dev_store<D, H>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+    dev_store<D, H, false>(out, cl2, wc0, g.n, C.c, Mout, Dout);
 }
 
 // Launch k of a tick: every lattice with k < nsteps advances one step.
@@ -1009,7 +1089,7 @@ struct PlainReader {
     }
 };
 
-template <int D, typename H, int RM>
+template <int D, typename H, bool GH, int RM>
 struct DevReader {
     const float* M;
     const H* Dv;
@@ -1017,7 +1097,7 @@ struct DevReader {
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double cl2) const
     {
         const float wc0 = 1.f / (float)cl2 - float(D);
-        return (double)dev_load<D, H>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0);
+        return (double)dev_load<D, H, GH>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0);
     }
 };
 
@@ -1217,7 +1297,7 @@ __global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E,
         for (int p = 0; p < P; ++p) pop[(int64_t)(i * P + p) * n + c] = (T)g0[i][p];
 }
 
-template <int D, typename H>
+template <int D, typename H, bool GH>
 __global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, const double* __restrict__ B,
                                                  const float* __restrict__ cl2a, int64_t n, float* M, H* Dv)
 {
@@ -1250,8 +1330,10 @@ __global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, c
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p) {
+            const int sl = dev_slot<D, GH>(i, p);
+            if (sl < 0) continue;
             const float d = (float)(g0[i][p] - (double)dev_eq<D>(i, p, Lf, Bf, wc0));
-            Dv[(int64_t)(i * P + p) * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
+            Dv[(int64_t)sl * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
         }
 }
 

@@ -39,7 +39,7 @@ bool valid_cfg(const lbem_config* c)
 {
     if (!c) return false;
     if (c->dim != 2 && c->dim != 3) return false;
-    if (c->prec < LBEM_F64 || c->prec > LBEM_BF16DEV) return false;
+    if (c->prec < LBEM_F64 || c->prec > LBEM_BF16GHOST) return false;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return false;
     if (c->dim == 2 && c->nz != 1) return false;
     if (c->nx > (1 << 30) || c->ny > (1 << 30) || c->nz > (1 << 30)) return false;
@@ -69,7 +69,8 @@ Sizes sizes_of(const lbem_config* c)
     if (c->prec <= LBEM_F32)
         s.pop_one = align256((size_t)Q * P * n * tm);
     else
-        s.pop_one = align256((size_t)(P + D) * n * 4) + align256((size_t)Q * P * n * 2);
+        s.pop_one = align256((size_t)(P + D) * n * 4) +
+                    align256((size_t)(c->prec >= LBEM_F16GHOST ? 2 * D * P - D : Q * P) * n * 2);
     s.copies = resolve_streaming(c) == LBEM_STREAM_AA ? 1 : 2;
     s.medium = align256(n * tm);
     s.mu = c->mu_varies ? align256(n * 8) + align256((size_t)D * n * tm) : 0;
@@ -322,7 +323,7 @@ struct PlainImpl : Impl {
     }
 };
 
-template <int D, typename H>
+template <int D, typename H, bool GH>
 struct DevImpl : Impl {
     static float* M(lbem_s* h, int k) { return (float*)h->pop[k]; }
     static H* Dv(lbem_s* h, int k)
@@ -340,7 +341,7 @@ struct DevImpl : Impl {
                 s.ent = h->zsrc_ent;
                 s.val = (const float*)h->zsrc_val;
                 s.amp = amp;
-                hipLaunchKernelGGL((k_step_dev3z<H, RM, MU>), dim3(h->zgeo.nblocks), dim3(NT), 0, h->stream,
+                hipLaunchKernelGGL((k_step_dev3z<H, GH, RM, MU>), dim3(h->zgeo.nblocks), dim3(NT), 0, h->stream,
                                    M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                                    (const float*)h->dlnmu, h->zgeo, h->zlz, s, (float)(1.0 / h->cfg.tau),
                                    (int)(h->cfg.tau == 0.5));
@@ -351,7 +352,7 @@ struct DevImpl : Impl {
         s.ent = h->src_ent;
         s.val = (const float*)h->src_val;
         s.amp = amp;
-        hipLaunchKernelGGL((k_step_dev<D, H, RM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
+        hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
                            M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
                            (int)(h->cfg.tau == 0.5));
@@ -380,16 +381,16 @@ struct DevImpl : Impl {
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         if (h->layout == LAYOUT_NATURAL)
-            return launch_fields<D, float>(h, DevReader<D, H, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n},
+            return launch_fields<D, float>(h, DevReader<D, H, GH, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n},
                                            E, B, partials);
-        return launch_fields<D, float>(h, DevReader<D, H, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n}, E,
+        return launch_fields<D, float>(h, DevReader<D, H, GH, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n}, E,
                                        B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
     {
         h->cur = 0;
         h->layout = LAYOUT_NATURAL;
-        hipLaunchKernelGGL((k_init_dev<D, H>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
+        hipLaunchKernelGGL((k_init_dev<D, H, GH>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
                            (const float*)h->cl2, h->n, M(h, 0), Dv(h, 0));
         return hipGetLastError();
     }
@@ -405,15 +406,19 @@ static Impl* make_impl(int D, int prec)
         switch (prec) {
             case LBEM_F64: return new (std::nothrow) PlainImpl<2, double>();
             case LBEM_F32: return new (std::nothrow) PlainImpl<2, float>();
-            case LBEM_F16DEV: return new (std::nothrow) DevImpl<2, __half>();
-            default: return new (std::nothrow) DevImpl<2, __hip_bfloat16>();
+            case LBEM_F16DEV: return new (std::nothrow) DevImpl<2, __half, false>();
+            case LBEM_BF16DEV: return new (std::nothrow) DevImpl<2, __hip_bfloat16, false>();
+            case LBEM_F16GHOST: return new (std::nothrow) DevImpl<2, __half, true>();
+            default: return new (std::nothrow) DevImpl<2, __hip_bfloat16, true>();
         }
     }
     switch (prec) {
         case LBEM_F64: return new (std::nothrow) PlainImpl<3, double>();
         case LBEM_F32: return new (std::nothrow) PlainImpl<3, float>();
-        case LBEM_F16DEV: return new (std::nothrow) DevImpl<3, __half>();
-        default: return new (std::nothrow) DevImpl<3, __hip_bfloat16>();
+        case LBEM_F16DEV: return new (std::nothrow) DevImpl<3, __half, false>();
+        case LBEM_BF16DEV: return new (std::nothrow) DevImpl<3, __hip_bfloat16, false>();
+        case LBEM_F16GHOST: return new (std::nothrow) DevImpl<3, __half, true>();
+        default: return new (std::nothrow) DevImpl<3, __hip_bfloat16, true>();
     }
 }
 
@@ -1151,6 +1156,7 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         const lbem_s* h = handles[i];
         if (!h || nsteps[i] < 0 || nsteps[i] > b->ksteps) return LBEM_EINVAL;
         if (h->nsrc != 0 || h->mu_set || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+        if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate kernels
         if (!h->have_fields) return LBEM_ESTATE;
         for (int j = 0; j < i; ++j)
             if (handles[j] == h) return LBEM_EINVAL;

@@ -124,7 +124,8 @@ def bytes_per_update(dim: int, prec: str) -> int:
         return 2 * Q * P * 4 + 4
     if prec == "f64":
         return 2 * Q * P * 8 + 8
-    return 2 * ((P + dim) * 4 + Q * P * 2) + 4
+    slots = (Q - 1) * P - dim if "ghost" in prec else Q * P
+    return 2 * ((P + dim) * 4 + slots * 2) + 4
 
 
 class Scheduler:

@@ -43,11 +43,17 @@ def test_strerror_and_required_bytes():
     bd = lbem.required_bytes(3, (64, 64, 64), "f16dev")
     m = 64 ** 3
     assert bd >= 2 * (6 * 4 + 21 * 2) * m
+    # ghost coordinates: 15 of the 21 deviations (3D), 2 of 5 (2D)
+    bg = lbem.required_bytes(3, (64, 64, 64), "bf16ghost")
+    assert bd - bg == 2 * 6 * 2 * m
+    assert (lbem.required_bytes(2, (256, 256, 1), "f16dev") -
+            lbem.required_bytes(2, (256, 256, 1), "f16ghost")) == 2 * 3 * 2 * 256 * 256
 
 
 @pytest.mark.parametrize("kw", [dict(dim=4), dict(dim=2, shape=(8, 8, 2)), dict(prec="f64", tau=0.0),
                                 dict(w0_vac=1.0), dict(w0_vac=-0.1), dict(shape=(0, 4, 1)),
-                                dict(prec="f16dev", streaming="aa"), dict(shape=(2048, 2048, 1024), dim=3)])
+                                dict(prec="f16dev", streaming="aa"), dict(prec="f16ghost", streaming="aa"),
+                                dict(prec=6), dict(shape=(2048, 2048, 1024), dim=3)])
 def test_invalid_configs_rejected_on_host(kw):
     args = dict(dim=2, shape=(8, 8, 1), prec="f32")
     args.update(kw)

@@ -63,10 +63,10 @@ def test_config3_full_256_fp32(streaming):
     sampled_parity(p, "f32", k, samples, 1e-5, streaming=streaming)
 
 
-@pytest.mark.parametrize("prec", ["f16dev"])
+@pytest.mark.parametrize("prec", ["f16dev", "f16ghost"])
 def test_config4_full_512_deviation_storage(prec):
     k = 16
     p = inputs.config4(nsteps=k)
-    announce("config4 512^3 f16dev full size")
+    announce(f"config4 512^3 {prec} full size")
     samples = [(256, 256, 256), (255, 258, 250), (511, 0, 300)]
     sampled_parity(p, prec, k, samples, 2e-3)

@@ -3,7 +3,8 @@ same seeded inputs.  Tolerances: relative L2 of E and of B <= 1e-12 for the
 FP64 format and <= 1e-5 for FP32 after up to 1000 steps.  The 16-bit
 deviation formats are judged in the energy norm
 sqrt(sum eps_abs|dE|^2 + |dB|^2/mu) / sqrt(sum eps_abs|E|^2 + |B|^2/mu)
-(<= 1e-3 FP16, <= 1e-2 BF16) with each field's relative L2 reported and held
+(<= 1e-3 FP16, <= 1e-2 BF16; the same for the ghost-coordinate variants of
+both) with each field's relative L2 reported and held
 to twice that: a field's own norm can pass through a temporal node (E in a
 resonant periodic box), where its relative error is not meaningful."""
 import numpy as np
@@ -14,7 +15,8 @@ from paper_1108_2651_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "bf16dev": 1e-2}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "bf16dev": 1e-2, "f16ghost": 1e-3, "bf16ghost": 1e-2}
+LOWP = ["f16dev", "bf16dev", "f16ghost", "bf16ghost"]
 
 
 def energy_norm_error(Eg, Bg, Eo, Bo, o, mu=None):
@@ -157,30 +159,30 @@ def test_aa_pull_and_tilings_bitwise(dim):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), v
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("prec", LOWP)
 def test_deviation_storage_config1(prec):
     p = inputs.config1()
     compare(p, 1000, prec)
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("prec", LOWP)
 def test_deviation_storage_3d_crop(prec):
     p = inputs.config3(nsteps=300, crop_n=32)
     compare(p, 300, prec)
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("prec", LOWP)
 def test_deviation_storage_ragged_mu(prec):
     # white-noise fields are far from equilibrium, so the 16-bit deviations
     # carry O(1) of each population: a code-path check with a looser bound
-    tol = 5e-3 if prec == "f16dev" else 4e-2
+    tol = 5e-3 if prec.startswith("f16") else 4e-2
     p = random_problem(3, (19, 13, 11), seed=90, mu=True, nsteps=40)
     compare(p, 40, prec, tol=tol)
     p2 = random_problem(2, (77, 29, 1), seed=91, mu=False, nsteps=40)
     compare(p2, 40, prec, tol=tol)
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("prec", LOWP)
 def test_deviation_tile_orders_bitwise(prec):
     """Strip / row-major tile orders and XCD remapping of the deviation kernel
     give identical results, with a source spread over many tiles."""
@@ -199,7 +201,7 @@ def test_deviation_zmarch_ragged_bitwise(shape, mu):
     """The z-marching 3D deviation kernel equals the per-cell gather kernel on
     ragged boxes (tiles wider than the box, chunks longer than nz, mu term)."""
     p = random_problem(3, shape, seed=sum(shape), mu=mu, nsteps=21)
-    for prec in ("f16dev", "bf16dev"):
+    for prec in LOWP:
         ref = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 0}).moments()
         for lz in (16, 4):
             announce(f"zmarch {shape} mu={mu} {prec} lz={lz}")

@@ -78,6 +78,11 @@ def test_batch_rejects_unsupported_members():
         b.run([s3, s3], [1, 1])                 # duplicate member
     with pytest.raises(lbem.LbemError):
         b.run([s3], [6])                        # more than steps_per_tick
+    s4 = lbem.Solver(2, q.shape, "f16ghost", streaming="pull", stream=st)
+    s4.setup(q)
+    with pytest.raises(lbem.LbemError) as e:
+        b.run([s4], [1])                        # no batched ghost-coordinate kernels
+    assert e.value.code == lbem.LBEM_EINVAL
     b.close()
 
 
