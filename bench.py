@@ -71,11 +71,11 @@ def _make_problem(name: str, nsteps: int):
         return I.config2(nsteps=nsteps)
     if name == "c1":
         return I.config1(nsteps=nsteps)
-    if name.startswith("2d"):          # "2d8192": the config2 medium tiled periodically
+    if name.startswith("2d"):          # "2d8192": the config2 medium tiled (or cropped) periodically
         n = int(name[2:])
         p = I.config2(nsteps=nsteps)
-        k = n // 2048
-        eps = np.tile(p.eps_r.reshape(2048, 2048), (k, k)).ravel()
+        k = max(1, n // 2048)
+        eps = np.tile(p.eps_r.reshape(2048, 2048), (k, k))[:n, :n].ravel()
         cells, w = I.line_source(n, n, 64)
         return I.Problem(dim=2, shape=(n, n, 1), eps_r=eps, mu_r=None, E0=np.zeros((3, n * n)),
                          B0=np.zeros((3, n * n)), src_comp=2, src_cells=cells, src_weights=w,
@@ -154,6 +154,62 @@ def cpu_baseline(p, budget_s: float = 15.0) -> dict:
                 seconds=el)
 
 
+def cpu_baseline_table(budget_s: float = 4.0) -> list:
+    """The FP64 oracle timed at one thread and at all host cores on the small
+    configurations: 2D 128^2 (FP64 pulse), 2D 2048^2 (the primary workload)
+    and the 64^3 centred crops of the two 3D media."""
+    from oracle import oracle as O
+    from paper_1108_2651_amd import inputs as I
+    allc = os.cpu_count() or 1
+    rows = []
+    probs = [("c1 128^2", I.config1(nsteps=400)), ("c2 2048^2", I.config2(nsteps=400)),
+             ("c3 64^3 crop", I.config3(nsteps=400, crop_n=64)), ("c4 64^3 crop", I.config4(nsteps=400, crop_n=64))]
+    for label, p in probs:
+        for threads in (1, allc):
+            used = O.set_threads(threads)
+            o = O.Oracle(p.dim, p.shape, p.tau, p.w0_vac)
+            o.set_medium(p.eps_r, p.mu_r)
+            o.init_fields(p.E0, p.B0)
+            has_src = len(p.src_cells) > 0
+            if has_src:
+                o.set_source(p.src_comp, p.src_cells, p.src_weights)
+            amp = p.amp if has_src else None
+            t = time.perf_counter()
+            o.step(1, amp[:1] if has_src else None)
+            per = time.perf_counter() - t
+            k = max(1, min(390, int(budget_s / max(per, 1e-9))))
+            t = time.perf_counter()
+            o.step(k, amp[1:1 + k] if has_src else None)
+            el = time.perf_counter() - t
+            rows.append(dict(workload=label, threads=used, steps=k, seconds=el,
+                             mlups=p.n * k / el / 1e6))
+            print(f"[bench] oracle {label} threads={used}: {rows[-1]['mlups']:.2f} MLUPS", file=sys.stderr,
+                  flush=True)
+    O.set_threads(allc)
+    return rows
+
+
+def size_sweep(steps: int = 100, warmup: int = 5) -> list:
+    """Roofline sweep across the Infinity-Cache boundary: 3D spheres medium
+    from 64^3 to 512^3 in FP32 (pull, fused pair; AA single steps) and the
+    two 16-bit formats; 2D from 512^2 to 8192^2 in FP32."""
+    rows = []
+    plan = [(f"3d{n}", prec, st) for n in (64, 96, 128, 160, 192, 256, 320, 384, 448, 512)
+            for prec, st in (("f32", "pull"), ("f32", "aa"), ("f16dev", "pull"), ("f16ghost", "pull"))]
+    plan += [(f"2d{n}", "f32", st) for n in (512, 1024, 2048, 4096, 8192) for st in ("pull", "aa")]
+    for name, prec, st in plan:
+        n = int(name[2:])
+        k = max(20, min(steps * 8, int(steps * (256 ** 3 if name.startswith("3d") else 2048 ** 2) /
+                                           (n ** 3 if name.startswith("3d") else n * n))))
+        try:
+            r = run_workload(name, prec, k, warmup, st, p=make_problem(name, 1100))
+        except Exception as e:  # report, do not hide
+            r = dict(workload=name, prec=prec, streaming=st, error=str(e))
+        print(json.dumps(r), flush=True)
+        rows.append(r)
+    return rows
+
+
 def load_traffic(name: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel sources."""
@@ -188,6 +244,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--only", default=None, help="workload:prec[:streaming], e.g. c2:f32 or c3:f16dev")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="size sweep (one JSON line per point) instead")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the oracle at 1 thread and all cores on the small configurations instead")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,6 +262,14 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+
+    if args.oracle_table:
+        print(json.dumps({"cpu_baseline_table": cpu_baseline_table()}), flush=True)
+        return
+
+    if args.sweep:
+        size_sweep()
         return
 
     if args.only:

@@ -52,11 +52,19 @@ bool valid_cfg(const lbem_config* c)
     return true;
 }
 
+// Boxes below this many cells (about 180^3) are served from the Infinity
+// Cache; there the 3D multi-step kernels cannot fill the chip and single steps
+// are faster (measured from 64^3 to 256^3).
+constexpr double SMALL3D = 6.0e6;
+
 int resolve_streaming(const lbem_config* c)
 {
-    // pull by default: the fused multi-step kernels need the second copy;
-    // the in-place AA pattern (half the memory) is available on request
+    // Pull by default: the fused multi-step kernels need the second copy.
+    // 3D FP64 never fuses and small 3D FP32 boxes run single steps: there the
+    // in-place AA pattern (half the memory) is as fast or faster.
     if (c->streaming != LBEM_STREAM_AUTO) return c->streaming;
+    const double n = (double)c->nx * (double)c->ny * (double)c->nz;
+    if (c->dim == 3 && (c->prec == LBEM_F64 || (c->prec == LBEM_F32 && n < SMALL3D))) return LBEM_STREAM_AA;
     return LBEM_STREAM_PULL;
 }
 
@@ -449,14 +457,19 @@ static void make_fused3_geo(lbem_s* h)
     // FP64 frames do not fit enough blocks per CU for the pair to pay off
     // (measured slower than single steps at 256^3), so FP64 runs single steps
     // unless asked for.
-    h->fuse_ns = env_int("LBEM_FUSE3", f64 ? 1 : 2) == 2 ? 2 : 1;
+    const bool small = (double)h->n < SMALL3D;
+    h->fuse_ns = env_int("LBEM_FUSE3", (f64 || small) ? 1 : 2) == 2 ? 2 : 1;
     h->f3_tx = env_int("LBEM_FUSE3_TX", f64 ? 32 : 64) == 64 && !f64 ? 64 : 32;
     h->f3_ty = NT / h->f3_tx;
-    h->f3_lz = std::max(1, env_int("LBEM_FUSE3_LZ", 32));
     Geo& g = h->fgeo;
     g = h->geo;
     g.tiles_x = (g.nx + h->f3_tx - 1) / h->f3_tx;
     g.tiles_y = (g.ny + h->f3_ty - 1) / h->f3_ty;
+    // longest z chunk (fewest recomputed boundary planes) that still gives
+    // enough blocks to fill 256 CUs
+    int lz = 32;
+    while (lz > 8 && (int64_t)g.tiles_x * g.tiles_y * ((g.nz + lz - 1) / lz) < 768) lz /= 2;
+    h->f3_lz = std::max(1, env_int("LBEM_FUSE3_LZ", lz));
     g.nblocks = g.tiles_x * g.tiles_y * ((g.nz + h->f3_lz - 1) / h->f3_lz);
     g.strip = 0;
     g.xcd = env_int("LBEM_FUSE3_XCD", 0);
@@ -491,7 +504,7 @@ static void make_fused_geo(lbem_s* h)
 
 static void make_zmarch_geo(lbem_s* h)
 {
-    h->zmarch = (h->D == 3 && h->prec >= LBEM_F16DEV) ? env_int("LBEM_DEV3Z", 1) : 0;
+    h->zmarch = (h->D == 3 && h->prec >= LBEM_F16DEV) ? env_int("LBEM_DEV3Z", (double)h->n >= SMALL3D) : 0;
     h->zlz = std::max(1, env_int("LBEM_DEV3Z_LZ", 16));
     Geo& g = h->zgeo;
     g = h->geo;

@@ -35,10 +35,16 @@ def test_strerror_and_required_bytes():
     b = lbem.required_bytes(2, (256, 256, 1), "f32")
     assert 2 * 5 * 4 * n + 4 * n + 24 * n <= b <= 2 * 5 * 4 * n + 4 * n + 24 * n + 4 * 256
     # the default is pull (two copies: the fused multi-step kernels need them);
-    # the in-place AA pattern keeps one copy of the 21 populations
-    b3 = lbem.required_bytes(3, (64, 64, 64), "f32")
-    assert b3 == lbem.required_bytes(3, (64, 64, 64), "f32", streaming="pull")
-    assert lbem.required_bytes(3, (64, 64, 64), "f32", streaming="aa") < b3
+    # the in-place AA pattern keeps one copy of the 21 populations, and is the
+    # default for 3D FP64 and for 3D FP32 boxes below 6e6 cells
+    b3 = lbem.required_bytes(3, (256, 256, 256), "f32")
+    assert b3 == lbem.required_bytes(3, (256, 256, 256), "f32", streaming="pull")
+    assert lbem.required_bytes(3, (256, 256, 256), "f32", streaming="aa") < b3
+    small = lbem.required_bytes(3, (64, 64, 64), "f32")
+    assert small == lbem.required_bytes(3, (64, 64, 64), "f32", streaming="aa")
+    assert lbem.required_bytes(3, (256, 256, 256), "f64") == \
+        lbem.required_bytes(3, (256, 256, 256), "f64", streaming="aa")
+    assert lbem.required_bytes(2, (64, 64, 1), "f64") == lbem.required_bytes(2, (64, 64, 1), "f64", streaming="pull")
     # deviation storage: FP32 moments (P+D) + 16-bit deviations (Q*P), two copies
     bd = lbem.required_bytes(3, (64, 64, 64), "f16dev")
     m = 64 ** 3

@@ -190,7 +190,7 @@ def test_deviation_tile_orders_bitwise(prec):
     ref = gpu_run(p, 30, prec, env={"LBEM_STRIP": 0, "LBEM_DEV3Z": 0}).moments()
     for env in ({"LBEM_STRIP": 4, "LBEM_DEV3Z": 0}, {"LBEM_STRIP": 2, "LBEM_XCD": 0, "LBEM_DEV3Z": 0},
                 {"LBEM_VEC": 2, "LBEM_STRIP": 3, "LBEM_DEV3Z": 0}, {"LBEM_DEV3Z": 1},
-                {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 3, "LBEM_DEV3Z_XCD": 0}, {"LBEM_DEV3Z_LZ": 1}):
+                {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 3, "LBEM_DEV3Z_XCD": 0}, {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 1}):
         announce(f"dev tile order {prec} {env}")
         got = gpu_run(p, 30, prec, env=env).moments()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
