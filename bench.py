@@ -34,16 +34,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(dim: int, prec: str) -> int:
+def bytes_per_cell(dim: int, prec: str, mu: bool = False) -> int:
     """Algorithmic HBM bytes per lattice update: every stored value read once
-    and written once, plus the c_L^2 medium read."""
+    and written once, plus the c_L^2 medium read (and the D components of
+    grad ln mu when mu varies)."""
     Q, P = 2 * dim + 1, dim * (dim - 1) // 2
+    tm = 8 if prec == "f64" else 4
+    extra = dim * tm if mu else 0
     if prec == "f64":
-        return 2 * Q * P * 8 + 8
+        return 2 * Q * P * 8 + 8 + extra
     if prec == "f32":
-        return 2 * Q * P * 4 + 4
+        return 2 * Q * P * 4 + 4 + extra
     slots = (Q - 1) * P - dim if "ghost" in prec else Q * P
-    return 2 * ((P + dim) * 4 + slots * 2) + 4
+    return 2 * ((P + dim) * 4 + slots * 2) + 4 + extra
 
 
 def kernel_source_hash() -> str:
@@ -88,6 +91,12 @@ def _make_problem(name: str, nsteps: int):
         return I.config4(nsteps=nsteps)
     if name.startswith("3d"):          # "3d128": spheres recipe at another size
         return I.config3(nsteps=nsteps, n=int(name[2:]))
+    if name in ("c2mu", "c3mu"):       # the same media with mu_r = 1 + (eps_r - 1)/3 as well
+        import copy
+        p = copy.copy(_make_problem(name[:2], nsteps))
+        p.mu_r = 1.0 + (p.eps_r - 1.0) / 3.0
+        p.name = p.name + "-mu"
+        return p
     raise ValueError(name)
 
 
@@ -101,7 +110,8 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
     if amp is None or len(amp) < warmup + steps:
         from paper_1108_2651_amd import inputs as I
         amp = I.ricker(warmup + steps, 1.0 / 80.0)
-    s = lbem.Solver(p.dim, p.shape, prec, tau=p.tau, w0_vac=p.w0_vac, streaming=streaming)
+    s = lbem.Solver(p.dim, p.shape, prec, tau=p.tau, w0_vac=p.w0_vac, streaming=streaming,
+                    mu_varies=p.mu_r is not None)
     s.setup(p)
     spl = s.steps_per_launch
     stream = torch.cuda.current_stream()
@@ -118,7 +128,7 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
     ms = e0.elapsed_time(e1)
     diag = s.energy(check=False)
     n = p.n
-    bpc = bytes_per_cell(p.dim, prec)
+    bpc = bytes_per_cell(p.dim, prec, p.mu_r is not None)
     st = streaming if streaming != "auto" else "pull"
     bpu = bpc / max(spl, 1)        # HBM bytes per cell update when spl steps share one pass
     mlups = n * steps / (ms * 1e-3) / 1e6
@@ -293,7 +303,9 @@ def main():
                 ("c3", "f16dev", "pull", 200, 10), ("c3", "bf16dev", "pull", 200, 10),
                 ("c3", "f16ghost", "pull", 200, 10),
                 ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5),
-                ("c4", "f16ghost", "pull", 50, 5)]
+                ("c4", "f16ghost", "pull", 50, 5),
+                ("c2mu", "f32", "pull", 1000, 20), ("c3mu", "f32", "auto", 200, 10),
+                ("c3mu", "f16ghost", "pull", 200, 10)]
         plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
         for name, prec, st, k, w in plan:
             print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)

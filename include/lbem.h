@@ -146,9 +146,32 @@ int lbem_energy(lbem_t h, double out[4]);
 int64_t lbem_time(lbem_t h);
 
 /* Time steps advanced per kernel launch by lbem_step on this handle (1, or 2-4
- * when the 2D plain formats fuse several steps into one pass through an LDS
- * tile; the result is identical to single steps).  EINVAL for NULL. */
+ * when the plain formats fuse several steps into one pass through LDS; the
+ * result is identical to single steps).  EINVAL for NULL. */
 int lbem_steps_per_launch(lbem_t h);
+
+/* ---- exact checkpoint / resume ----
+ * Not an operation of the paper: it lets a long solve stop and continue bit
+ * for bit.  The blob is a 128-byte header (magic "LBEMST01", dim, format,
+ * streaming, storage layout, nx, ny, nz, time, payload size) followed by the
+ * handle's population state exactly as stored (format- and streaming-
+ * specific; it is not converted).  The medium and the current source are not
+ * in the blob: the resuming handle is created with the same configuration and
+ * given the same lbem_set_medium / lbem_set_source before lbem_set_state. */
+
+/* Size in bytes of the state blob of this handle (0 for NULL). */
+size_t lbem_state_bytes(lbem_t h);
+
+/* Write the state blob into buf (bytes >= lbem_state_bytes).  on_device == 0:
+ * host memory, else device memory on the handle's device.  Synchronises.
+ * Errors: EINVAL (NULL, too small), ESTATE (no fields yet), EDEVICE. */
+int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device);
+
+/* Restore a blob written by lbem_get_state on a handle of the same dim,
+ * format, streaming and box: populations, storage layout and time.  Requires
+ * lbem_set_medium first (ESTATE); EINVAL for a blob of another configuration
+ * or a bad header.  Synchronises; afterwards the handle is initialised. */
+int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device);
 
 /* Static description of a status code. */
 const char* lbem_strerror(int code);

@@ -337,9 +337,10 @@ struct AmpPack {
     T a[NS];             // source amplitude of each fused step
 };
 
-template <typename T, int NS, int TY>
+template <typename T, int NS, int TY, bool MU>
 __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
-                                                    const Geo g, const FusedSrc<T> fs, const AmpPack<T, NS> amps,
+                                                    const T* __restrict__ dlnmu, const Geo g,
+                                                    const FusedSrc<T> fs, const AmpPack<T, NS> amps,
                                                     const T omega, const int tau_half)
 {
     constexpr int H = NS - 1;
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
     __shared__ T lp[NB][Q][FC];
     __shared__ T lc[FC];
     __shared__ T ls[FC];
+    __shared__ T ldl[MU ? 2 : 1][MU ? FC : 1];   // grad ln mu of the frame
 
     const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
     const int tx = b % g.tiles_x, ty = b / g.tiles_x;
@@ -378,6 +380,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         constexpr int C0 = (FC + NT - 1) / NT;
         T fv0[C0][Q][1];
         T cl0[C0];
+        T dl0[C0][2];
 #pragma unroll
         for (int j = 0; j < C0; ++j) {
             const int k = threadIdx.x + j * NT;
@@ -390,6 +393,10 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 #pragma unroll
                 for (int i = 0; i < Q; ++i) fv0[j][i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
                 cl0[j] = cl2a[C.c];
+                if (MU) {
+                    dl0[j][0] = dlnmu[C.c];
+                    dl0[j][1] = dlnmu[(int64_t)g.n + C.c];
+                }
             }
         }
         const T amp = has_src ? amps.a[0] : T(0);
@@ -400,7 +407,12 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
                 T rho[1], K[2], Sp[1], o[Q][1];
                 moments<2, T>(fv0[j], rho, K);
                 Sp[0] = has_src ? ls[k] * amp : T(0);
-                collide<2, T>(fv0[j], cl0[j], Sp, has_src, omega, tau_half != 0, rho, K, o);
+                if (MU) {
+                    add_mu_source<2, T>(K, cl0[j], dl0[j], Sp);
+                    ldl[0][k] = dl0[j][0];
+                    ldl[MU ? 1 : 0][k] = dl0[j][1];
+                }
+                collide<2, T>(fv0[j], cl0[j], Sp, has_src || MU, omega, tau_half != 0, rho, K, o);
                 lc[k] = cl0[j];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) lp[0][i][k] = o[i][0];
@@ -430,8 +442,12 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
             T rho[1], K[2], Sp[1];
             moments<2, T>(fv, rho, K);
             Sp[0] = has_src ? ls[f] * amp : T(0);
+            if (MU) {
+                const T dl[2] = {ldl[0][f], ldl[MU ? 1 : 0][f]};
+                add_mu_source<2, T>(K, cl2, dl, Sp);
+            }
             T o[Q][1];
-            collide<2, T>(fv, cl2, Sp, has_src, omega, tau_half != 0, rho, K, o);
+            collide<2, T>(fv, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, o);
             if (st == NS - 1) {
                 const int gx = x0 + fx, gy = y0 + fy;    // inside the tile: no wrap needed
                 if (gx < g.nx && gy < g.ny) {
@@ -458,10 +474,11 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // components (ring of 3 planes) and -z components (one plane); then it runs
 // step 2 on plane zz-1 of the tile, pulling from LDS, and writes it.  Every
 // update is the same collide() as the single-step kernel: bit-identical.
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool MU>
 __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
-                                                    const Geo g, const int lz, const FusedSrc<T> fs,
-                                                    const AmpPack<T, 2> amps, const T omega, const int tau_half)
+                                                    const T* __restrict__ dlnmu, const Geo g, const int lz,
+                                                    const FusedSrc<T> fs, const AmpPack<T, 2> amps,
+                                                    const T omega, const int tau_half)
 {
     constexpr int D = 3, Q = 7, P = 3;
     constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;
@@ -521,7 +538,13 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
             moments<D, T>(f, rho, K);
 #pragma unroll
             for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[bi][p][k] * amps.a[0] : T(0);
-            collide<D, T>(f, cl2, Sp, has_src, omega, tau_half != 0, rho, K, out);
+            if (MU) {
+                T dl[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
+                add_mu_source<D, T>(K, cl2, dl, Sp);
+            }
+            collide<D, T>(f, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, out);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int sl = ipl(i);
@@ -564,7 +587,13 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
                 moments<D, T>(f, rho, K);
 #pragma unroll
                 for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[pb][p][hc] * amps.a[1] : T(0);
-                collide<D, T>(f, cl2, Sp, has_src, omega, tau_half != 0, rho, K, out);
+                if (MU) {
+                    T dl[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + c];
+                    add_mu_source<D, T>(K, cl2, dl, Sp);
+                }
+                collide<D, T>(f, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, out);
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
 #pragma unroll

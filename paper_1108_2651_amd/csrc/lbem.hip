@@ -190,8 +190,8 @@ static hipError_t launch_fields(lbem_s* h, const R& rd, double* E, double* B, do
 }
 
 // fused 2D launches: (steps per launch, tile rows) pairs that are instantiated
-template <typename T, int NS, int TY>
-static hipError_t go_fused_nt(lbem_s* h, const T* src, T* dst, const double* amp)
+template <typename T, int NS, int TY, bool MU>
+static hipError_t go_fused_ntm(lbem_s* h, const T* src, T* dst, const double* amp)
 {
     FusedSrc<T> fs;
     fs.off = h->nfsrc ? h->fsrc_off : nullptr;
@@ -199,9 +199,17 @@ static hipError_t go_fused_nt(lbem_s* h, const T* src, T* dst, const double* amp
     fs.val = (const T*)h->fsrc_val;
     AmpPack<T, NS> a;
     for (int j = 0; j < NS; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
-    hipLaunchKernelGGL((k_step_fused2d<T, NS, TY>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src, dst,
-                       (const T*)h->cl2, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau), (int)(h->cfg.tau == 0.5));
+    hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src,
+                       dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau),
+                       (int)(h->cfg.tau == 0.5));
     return hipGetLastError();
+}
+
+template <typename T, int NS, int TY>
+static hipError_t go_fused_nt(lbem_s* h, const T* src, T* dst, const double* amp)
+{
+    if (h->mu_set) return go_fused_ntm<T, NS, TY, true>(h, src, dst, amp);
+    return go_fused_ntm<T, NS, TY, false>(h, src, dst, amp);
 }
 
 template <typename T>
@@ -223,7 +231,7 @@ static hipError_t go_fused(lbem_s* h, const T* src, T* dst, const double* amp)
     return hipErrorInvalidValue;
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool MU>
 static hipError_t go_fused3_t(lbem_s* h, const T* src, T* dst, const double* amp)
 {
     FusedSrc<T> fs;
@@ -232,22 +240,26 @@ static hipError_t go_fused3_t(lbem_s* h, const T* src, T* dst, const double* amp
     fs.val = (const T*)h->fsrc_val;
     AmpPack<T, 2> a;
     for (int j = 0; j < 2; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
-    hipLaunchKernelGGL((k_step_fused3d<T, TX, TY>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src, dst,
-                       (const T*)h->cl2, h->fgeo, h->f3_lz, fs, a, (T)(1.0 / h->cfg.tau),
-                       (int)(h->cfg.tau == 0.5));
+    hipLaunchKernelGGL((k_step_fused3d<T, TX, TY, MU>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src,
+                       dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, h->f3_lz, fs, a,
+                       (T)(1.0 / h->cfg.tau), (int)(h->cfg.tau == 0.5));
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t go_fused3(lbem_s* h, const T* src, T* dst, const double* amp)
 {
-    if (h->f3_tx == 64) return go_fused3_t<T, 64, 4>(h, src, dst, amp);
-    return go_fused3_t<T, 32, 8>(h, src, dst, amp);
+    if (h->mu_set) {
+        if (h->f3_tx == 64) return go_fused3_t<T, 64, 4, true>(h, src, dst, amp);
+        return go_fused3_t<T, 32, 8, true>(h, src, dst, amp);
+    }
+    if (h->f3_tx == 64) return go_fused3_t<T, 64, 4, false>(h, src, dst, amp);
+    return go_fused3_t<T, 32, 8, false>(h, src, dst, amp);
 }
 
 static bool fused_ok(const lbem_s* h)
 {
-    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && !h->mu_set && h->fuse_ns > 1;
+    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1;
 }
 
 template <int D, typename T>
@@ -1027,6 +1039,85 @@ int lbem_steps_per_launch(lbem_t h)
 {
     if (!h) return LBEM_EINVAL;
     return fused_ok(h) ? h->fuse_ns : 1;
+}
+
+namespace {
+constexpr size_t STATE_HDR = 128;
+struct StateHeader {
+    char magic[8];
+    int32_t dim, prec, streaming, layout;
+    int64_t nx, ny, nz, t;
+    uint64_t payload;
+};
+static_assert(sizeof(StateHeader) <= STATE_HDR, "state header");
+const char STATE_MAGIC[8] = {'L', 'B', 'E', 'M', 'S', 'T', '0', '1'};
+}  // namespace
+
+size_t lbem_state_bytes(lbem_t h)
+{
+    if (!h) return 0;
+    return STATE_HDR + sizes_of(&h->cfg).pop_one;
+}
+
+int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device)
+{
+    if (!h || !buf || bytes < lbem_state_bytes(h)) return LBEM_EINVAL;
+    if (!h->have_fields) return LBEM_ESTATE;
+    char hdr[STATE_HDR] = {0};
+    StateHeader sh{};
+    std::memcpy(sh.magic, STATE_MAGIC, 8);
+    sh.dim = h->D;
+    sh.prec = h->prec;
+    sh.streaming = h->streaming;
+    sh.layout = h->layout;
+    sh.nx = h->cfg.nx;
+    sh.ny = h->cfg.ny;
+    sh.nz = h->cfg.nz;
+    sh.t = h->t;
+    sh.payload = sizes_of(&h->cfg).pop_one;
+    std::memcpy(hdr, &sh, sizeof(sh));
+    char* out = (char*)buf;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (on_device) {
+        HIP_OK(hipMemcpyAsync(out, hdr, STATE_HDR, hipMemcpyHostToDevice, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));  // hdr is on this stack frame
+    } else {
+        std::memcpy(out, hdr, STATE_HDR);
+    }
+    HIP_OK(hipMemcpyAsync(out + STATE_HDR, h->pop[h->cur], sh.payload, k, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return LBEM_OK;
+}
+
+int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
+{
+    if (!h || !buf || bytes < lbem_state_bytes(h)) return LBEM_EINVAL;
+    if (!h->have_medium) return LBEM_ESTATE;
+    const char* in = (const char*)buf;
+    StateHeader sh{};
+    if (on_device) {
+        HIP_OK(hipMemcpyAsync(&sh, in, sizeof(sh), hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    } else {
+        std::memcpy(&sh, in, sizeof(sh));
+    }
+    const size_t pay = sizes_of(&h->cfg).pop_one;
+    if (std::memcmp(sh.magic, STATE_MAGIC, 8) != 0 || sh.dim != h->D || sh.prec != h->prec ||
+        sh.streaming != h->streaming || sh.nx != h->cfg.nx || sh.ny != h->cfg.ny || sh.nz != h->cfg.nz ||
+        sh.payload != pay || sh.t < 0 || sh.layout < LAYOUT_NATURAL || sh.layout > LAYOUT_AA_SWAPPED)
+        return LBEM_EINVAL;
+    // pull steps never leave the AA layout, AA steps never the pull one
+    if ((h->streaming == LBEM_STREAM_PULL && sh.layout == LAYOUT_AA_SWAPPED) ||
+        (h->streaming == LBEM_STREAM_AA && sh.layout == LAYOUT_PULL_PENDING))
+        return LBEM_EINVAL;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_OK(hipMemcpyAsync(h->pop[0], in + STATE_HDR, pay, k, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    h->cur = 0;
+    h->layout = sh.layout;
+    h->t = sh.t;
+    h->have_fields = true;
+    return LBEM_OK;
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_medium",
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
            "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
-           "lbem_steps_per_launch")
+           "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state")
 
 
 class Config(C.Structure):
@@ -66,6 +66,10 @@ def load():
     L.lbem_time.argtypes = [vp]
     L.lbem_time.restype = i64
     L.lbem_steps_per_launch.argtypes = [vp]
+    L.lbem_state_bytes.argtypes = [vp]
+    L.lbem_state_bytes.restype = C.c_size_t
+    L.lbem_get_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
+    L.lbem_set_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
     L.lbem_strerror.argtypes = [C.c_int]
     L.lbem_strerror.restype = C.c_char_p
     _lib = L
@@ -210,6 +214,32 @@ class Solver:
         if check:
             self._chk(rc, "lbem_energy")
         return dict(energy=out[0], qc=out[1], divb2=out[2], b2=out[3], status=rc)
+
+    # -- checkpoint / resume -------------------------------------------------
+    def state_bytes(self) -> int:
+        return int(load().lbem_state_bytes(self._h))
+
+    def get_state(self, out=None):
+        """The exact state blob: into ``out`` (a uint8 numpy array, or a uint8
+        device tensor) if given, else a new numpy array."""
+        nb = self.state_bytes()
+        if out is None:
+            out = np.empty(nb, dtype=np.uint8)
+        if isinstance(out, np.ndarray):
+            self._chk(load().lbem_get_state(self._h, _ptr(out), out.nbytes, 0), "lbem_get_state")
+        else:
+            self._chk(load().lbem_get_state(self._h, C.c_void_p(out.data_ptr()), out.numel(), 1),
+                      "lbem_get_state")
+        return out
+
+    def set_state(self, blob):
+        """Restore a blob from ``get_state`` (numpy uint8 array or device tensor)."""
+        if isinstance(blob, np.ndarray):
+            b = np.ascontiguousarray(blob, dtype=np.uint8)
+            self._chk(load().lbem_set_state(self._h, _ptr(b), b.nbytes, 0), "lbem_set_state")
+        else:
+            self._chk(load().lbem_set_state(self._h, C.c_void_p(blob.data_ptr()), blob.numel(), 1),
+                      "lbem_set_state")
 
     @property
     def t(self) -> int:

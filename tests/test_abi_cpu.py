@@ -78,3 +78,6 @@ def test_null_handle_calls():
     assert L.lbem_time(None) == -1
     assert L.lbem_step(None, 1, None) == lbem.LBEM_EINVAL
     assert L.lbem_moments(None, None, None, 0) == lbem.LBEM_EINVAL
+    assert L.lbem_state_bytes(None) == 0
+    assert L.lbem_get_state(None, None, 0, 0) == lbem.LBEM_EINVAL
+    assert L.lbem_set_state(None, None, 0, 0) == lbem.LBEM_EINVAL

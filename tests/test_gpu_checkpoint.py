@@ -1,0 +1,87 @@
+"""Exact checkpoint / resume through lbem_get_state / lbem_set_state: a solve
+stopped, saved, restored into a fresh handle and continued equals the solve
+run straight through, bit for bit, in every format and streaming pattern
+(odd step counts leave AA mid-pair and fused multi-step launches mid-way)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, random_problem
+from paper_1108_2651_amd import lbem
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(2, (70, 33, 1), "f64", "pull"), (2, (96, 40, 1), "f32", "pull"), (2, (64, 48, 1), "f32", "aa"),
+         (2, (50, 31, 1), "f16ghost", "pull"), (3, (24, 20, 18), "f32", "aa"), (3, (24, 20, 18), "f32", "pull"),
+         (3, (19, 13, 11), "f64", "aa"), (3, (20, 16, 12), "bf16dev", "pull"), (3, (20, 16, 12), "f16ghost", "pull")]
+
+
+def make(p, prec, streaming):
+    s = lbem.Solver(p.dim, p.shape, prec, w0_vac=p.w0_vac, streaming=streaming)
+    s.set_medium(p.eps_r)
+    s.set_source(p.src_comp, p.src_cells, p.src_weights)
+    return s
+
+
+@pytest.mark.parametrize("dim,shape,prec,streaming", CASES)
+def test_resume_is_bitwise(dim, shape, prec, streaming):
+    announce(f"checkpoint {dim}D {shape} {prec} {streaming}")
+    p = random_problem(dim, shape, seed=sum(shape) + 7, nsteps=60)
+    a = make(p, prec, streaming)
+    a.init_fields(p.E0, p.B0)
+    a.step(60, p.amp[:60])
+    Ea, Ba = a.moments()
+    a.close()
+
+    b = make(p, prec, streaming)
+    b.init_fields(p.E0, p.B0)
+    b.step(23, p.amp[:23])
+    blob = b.get_state()
+    assert blob.size == b.state_bytes()
+    b.close()
+
+    c = make(p, prec, streaming)
+    c.set_state(blob)
+    assert c.t == 23
+    c.step(37, p.amp[23:60])
+    Ec, Bc = c.moments()
+    assert np.array_equal(Ea, Ec) and np.array_equal(Ba, Bc)
+    c.close()
+
+
+def test_state_on_device_and_rejections():
+    import torch
+    p = random_problem(2, (40, 24, 1), seed=3, nsteps=20)
+    a = make(p, "f32", "pull")
+    a.init_fields(p.E0, p.B0)
+    a.step(9, p.amp[:9])
+    dev = torch.empty(a.state_bytes(), dtype=torch.uint8, device="cuda")
+    a.get_state(dev)
+    host = a.get_state()
+    assert np.array_equal(dev.cpu().numpy(), host)
+    b = make(p, "f32", "pull")
+    b.set_state(dev)
+    assert b.t == 9
+    a.step(11, p.amp[9:20])
+    b.step(11, p.amp[9:20])
+    assert all(np.array_equal(x, y) for x, y in zip(a.moments(), b.moments()))
+    # another format, another box, a damaged header, a missing medium
+    for other in (lbem.Solver(2, (40, 24, 1), "f64"), lbem.Solver(2, (40, 25, 1), "f32")):
+        other.set_medium(np.ones(other.n))
+        with pytest.raises(lbem.LbemError) as e:
+            other.set_state(host)
+        assert e.value.code == lbem.LBEM_EINVAL
+        other.close()
+    bad = host.copy()
+    bad[0] ^= 0xFF
+    with pytest.raises(lbem.LbemError) as e:
+        b.set_state(bad)
+    assert e.value.code == lbem.LBEM_EINVAL
+    fresh = lbem.Solver(2, (40, 24, 1), "f32")
+    with pytest.raises(lbem.LbemError) as e:
+        fresh.set_state(host)
+    assert e.value.code == lbem.LBEM_ESTATE
+    with pytest.raises(lbem.LbemError) as e:
+        fresh.get_state()
+    assert e.value.code == lbem.LBEM_ESTATE
+    for s in (a, b, fresh):
+        s.close()

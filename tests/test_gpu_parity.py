@@ -77,27 +77,33 @@ def test_ragged_shapes_all_terms(dim, shape, mu):
     compare(p, 61, "f32", "auto", tol=2e-5)
 
 
+@pytest.mark.parametrize("mu", [False, True])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("shape", [(96, 40, 1), (100, 37, 1), (1, 64, 1), (300, 2, 1), (130, 70, 1)])
-def test_temporal_blocking_bitwise(prec, shape):
+def test_temporal_blocking_bitwise(prec, shape, mu):
     """2, 3 or 4 fused time steps per launch (LDS frame with halo, periodic
-    images of sources included) equal the same number of single steps bit for
-    bit, for ragged and tiny lattices and odd step counts."""
-    p = random_problem(2, shape, seed=sum(shape) + 11, nsteps=53)
+    images of sources included, with or without the mu-gradient source)
+    equal the same number of single steps bit for bit, for ragged and tiny
+    lattices and odd step counts."""
+    p = random_problem(2, shape, seed=sum(shape) + 11, mu=mu, nsteps=53)
     ref = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": 1}).moments()
     combos = [(2, 16), (2, 8), (2, 4), (3, 16), (4, 16), (4, 8)] if prec == "f32" else [(2, 8), (2, 4), (3, 8)]
     for ns, ty in combos:
         announce(f"fused {prec} {shape} ns={ns} ty={ty}")
-        got = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": ns, "LBEM_FUSE_TY": ty}).moments()
+        s = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": ns, "LBEM_FUSE_TY": ty})
+        assert s.steps_per_launch == ns
+        got = s.moments()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (ns, ty)
 
 
+@pytest.mark.parametrize("mu", [False, True])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("shape", [(40, 24, 20), (70, 9, 5), (33, 17, 37), (5, 3, 7), (128, 4, 2)])
-def test_temporal_blocking_3d_bitwise(prec, shape):
+def test_temporal_blocking_3d_bitwise(prec, shape, mu):
     """Two fused 3D steps per launch (z-marching, LDS plane rings, sources
-    with periodic images) equal two single steps bit for bit."""
-    p = random_problem(3, shape, seed=sum(shape) + 13, nsteps=31)
+    with periodic images, mu-gradient source) equal two single steps bit for
+    bit."""
+    p = random_problem(3, shape, seed=sum(shape) + 13, mu=mu, nsteps=31)
     ref = gpu_run(p, 31, prec, "pull", env={"LBEM_FUSE3": 1}).moments()
     combos = [dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=32), dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=3),
               dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=1)]
