@@ -35,6 +35,20 @@
  *    equilibrium of the initial fields.
  *  - 3D velocity order 0,+x,+y,+z,-x,-y,-z; 2D order of the paper
  *    (0,(1,0),(0,1),(-1,0),(0,-1)).
+ *  - Non-periodic faces (the paper treats periodic boxes only and leaves
+ *    other boundaries open): a wall sits half a cell outside the first and
+ *    last cell of an axis.  A perfectly conducting (PEC) wall is the mirror
+ *    image of the box: the population that would leave through the face
+ *    re-enters the same cell along the opposite velocity, with each tensor
+ *    component transformed as a tensor under the reflection of that axis
+ *    (sign -1 where alpha or beta is the normal axis), so tangential E is odd
+ *    and normal E even about the wall.  A PMC wall takes the opposite sign.
+ *    Beside a wall the medium is mirrored too (the ln mu gradient uses the
+ *    cell itself for the missing neighbour).
+ *  - Absorbing layer: after collision every population of a cell is
+ *    multiplied by 1 - sigma(x); E and B decay at the same rate, so the
+ *    layer's electric and magnetic losses stay in the ratio eps : mu (an
+ *    impedance-matched absorber).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
  */
@@ -64,6 +78,8 @@ typedef struct {
     double *dlnmu;        /* [3][n] central-difference gradient of ln mu */
     double *g, *gs;       /* [n][Q][D][D] populations, streamed copy */
     double *jd;           /* [3][n] current-density footprint (weights) */
+    double *keep;         /* [n] 1 - sigma of the absorbing layer, or NULL */
+    int bc[3];            /* per axis: 0 periodic, 1 PEC wall, 2 PMC wall */
     long t;
     int have_medium, have_fields, has_mu;
 } orc_t;
@@ -105,6 +121,18 @@ static long neighbour(const orc_t* o, long x, const int* d, int sign)
     iy = wrap(iy + sign * d[1], o->ny);
     iz = wrap(iz + sign * d[2], o->nz);
     return ix + o->nx * (iy + o->ny * iz);
+}
+
+/* Neighbour for the ln mu gradient: beyond a wall the mirror image of the
+ * missing cell is the cell itself. */
+static long medium_neighbour(const orc_t* o, long x, int k, int sign)
+{
+    long ix = x % o->nx, iy = (x / o->nx) % o->ny, iz = x / (o->nx * o->ny);
+    long v[3] = {ix, iy, iz}, nn[3] = {o->nx, o->ny, o->nz};
+    long w = v[k] + sign;
+    if (o->bc[k] != 0 && (w < 0 || w >= nn[k])) w = v[k];
+    v[k] = wrap(w, nn[k]);
+    return v[0] + o->nx * (v[1] + o->ny * v[2]);
 }
 
 #define GI(o, x, i, a, b) ((((size_t)(x) * (o)->Q + (i)) * (o)->D + (a)) * (o)->D + (b))
@@ -217,6 +245,7 @@ orc_t* orc_create(int D, long nx, long ny, long nz, double tau, double w0_vac)
 
 void orc_destroy(orc_t* o)
 {
+    if (o) free(o->keep);
     if (!o) return;
     free(o->cL2); free(o->w0); free(o->eps_abs); free(o->mu_r); free(o->dlnmu);
     free(o->g); free(o->gs); free(o->jd); free(o);
@@ -253,10 +282,8 @@ int orc_set_medium(orc_t* o, const double* eps_r, const double* mu_r)
     }
     for (long x = 0; x < o->n; ++x)
         for (int k = 0; k < 3; ++k) {
-            int d[3] = {0, 0, 0};
-            d[k] = 1;
             if (k >= D) { o->dlnmu[k * o->n + x] = 0.0; continue; }
-            long xp = neighbour(o, x, d, +1), xm = neighbour(o, x, d, -1);
+            long xp = medium_neighbour(o, x, k, +1), xm = medium_neighbour(o, x, k, -1);
             o->dlnmu[k * o->n + x] = 0.5 * (log(o->mu_r[xp]) - log(o->mu_r[xm]));
         }
     o->have_medium = 1;
@@ -330,15 +357,62 @@ int orc_step(orc_t* o, long nsteps, const double* amp)
                 S[gm] = cM2 * mu_term - a * o->jd[gm * n + x] / o->eps_abs[x];
             }
             collide_cell(D, o->c, o->w0[x], o->cL2[x], o->tau, &o->g[GI(o, x, 0, 0, 0)], S, out);
-            /* streaming, eq. STREAM: g(x + c_i, t+1) = g'(x, t) */
+            if (o->keep)
+                for (int k = 0; k < Q * D * D; ++k) out[k] *= o->keep[x];
+            /* streaming, eq. STREAM: g(x + c_i, t+1) = g'(x, t); through a wall
+             * face: back into x along the opposite velocity, reflected */
+            long v[3] = {x % o->nx, (x / o->nx) % o->ny, x / (o->nx * o->ny)};
+            long nn[3] = {o->nx, o->ny, o->nz};
             for (int i = 0; i < Q; ++i) {
-                long xd = neighbour(o, x, o->c[i], +1);
-                for (int k = 0; k < D * D; ++k) o->gs[GI(o, xd, i, 0, 0) + k] = out[i * D * D + k];
+                int wall = -1;
+                for (int a = 0; a < D; ++a)
+                    if (o->c[i][a] != 0 && o->bc[a] != 0 && (v[a] + o->c[i][a] < 0 || v[a] + o->c[i][a] >= nn[a]))
+                        wall = a;
+                if (wall < 0) {
+                    long xd = neighbour(o, x, o->c[i], +1);
+                    for (int k = 0; k < D * D; ++k) o->gs[GI(o, xd, i, 0, 0) + k] = out[i * D * D + k];
+                } else {
+                    int io = 0;
+                    for (int j = 1; j < Q; ++j)
+                        if (o->c[j][wall] == -o->c[i][wall]) io = j;
+                    double flip = o->bc[wall] == 1 ? -1.0 : 1.0;
+                    for (int a = 0; a < D; ++a)
+                        for (int b = 0; b < D; ++b) {
+                            double sg = (a == wall || b == wall) ? flip : -flip;
+                            o->gs[GI(o, x, io, a, b)] = sg * out[(i * D + a) * D + b];
+                        }
+                }
             }
         }
         double* tmp = o->g; o->g = o->gs; o->gs = tmp;
         o->t += 1;
     }
+    return ORC_OK;
+}
+
+/* Boundary kind of one axis (0 periodic, 1 PEC wall, 2 PMC wall); before the
+ * medium is set, since the ln mu gradient beside a wall depends on it. */
+int orc_set_boundary(orc_t* o, int axis, int kind)
+{
+    if (axis < 0 || axis >= o->D || kind < 0 || kind > 2) return ORC_EINVAL;
+    if (o->have_medium) return ORC_ESTATE;
+    o->bc[axis] = kind;
+    return ORC_OK;
+}
+
+/* Absorbing layer: per-cell sigma in [0,1) (NULL removes it). */
+int orc_set_absorber(orc_t* o, const double* sigma)
+{
+    if (!sigma) {
+        free(o->keep);
+        o->keep = NULL;
+        return ORC_OK;
+    }
+    for (long x = 0; x < o->n; ++x)
+        if (!(sigma[x] >= 0.0 && sigma[x] < 1.0)) return ORC_EINVAL;
+    if (!o->keep) o->keep = (double*)malloc(sizeof(double) * o->n);
+    if (!o->keep) return ORC_ENOMEM;
+    for (long x = 0; x < o->n; ++x) o->keep[x] = 1.0 - sigma[x];
     return ORC_OK;
 }
 

@@ -50,6 +50,8 @@ def lib():
         L.orc_equilibrium.argtypes = [C.c_int, C.c_double, dp, dp, dp]
         L.orc_collide.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
         L.orc_velocities.argtypes = [C.c_int, np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")]
+        L.orc_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_set_absorber.argtypes = [C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -118,6 +120,22 @@ class Oracle:
         else:
             mu = np.ascontiguousarray(mu_r, np.float64).ravel()
             _chk(lib().orc_set_medium(self._h, eps, mu.ctypes.data_as(C.c_void_p)))
+
+    BOUNDARY = {"periodic": 0, "pec": 1, "pmc": 2}
+
+    def set_boundary(self, axis: int, kind: str):
+        """Walls on both faces of ``axis`` (before set_medium): 'pec' (the box's
+        mirror image, tangential E odd), 'pmc' (the opposite), 'periodic'."""
+        _chk(lib().orc_set_boundary(self._h, int(axis), self.BOUNDARY[kind]))
+
+    def set_absorber(self, sigma=None):
+        """Absorbing layer: every post-collision population of a cell is
+        multiplied by 1 - sigma(x); None removes it."""
+        if sigma is None:
+            _chk(lib().orc_set_absorber(self._h, None))
+        else:
+            s = np.ascontiguousarray(sigma, np.float64).ravel()
+            _chk(lib().orc_set_absorber(self._h, s.ctypes.data_as(C.c_void_p)))
 
     def init_fields(self, E, B):
         _chk(lib().orc_init_fields(self._h, np.ascontiguousarray(E, np.float64).reshape(-1),
