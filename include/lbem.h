@@ -65,6 +65,13 @@ typedef enum {
     LBEM_BF16GHOST = 5 /* as LBEM_F16GHOST with BF16 ghost coordinates           */
 } lbem_prec;
 
+/* Kind of the two faces of one axis (lbem_set_boundary). */
+typedef enum {
+    LBEM_BC_PERIODIC = 0, /* the paper's periodic box                            */
+    LBEM_BC_PEC = 1,      /* perfectly conducting walls: tangential E = 0        */
+    LBEM_BC_PMC = 2       /* perfectly magnetic walls: tangential B = 0          */
+} lbem_boundary;
+
 /* Streaming pattern (eq. STREAM) of the stored populations. */
 typedef enum {
     LBEM_STREAM_AUTO = 0, /* pull (the multi-step fused kernels need two copies),
@@ -172,6 +179,31 @@ int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device);
  * lbem_set_medium first (ESTATE); EINVAL for a blob of another configuration
  * or a bad header.  Synchronises; afterwards the handle is initialised. */
 int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device);
+
+/* ---- non-periodic faces and absorbing layer ----
+ * Not in the paper, which uses periodic boxes and leaves other boundaries to
+ * future work.  Walls sit half a cell outside the first and last cell of an
+ * axis.  A population that would stream in from beyond a wall is the cell's
+ * own outgoing population along the opposite velocity, reflected as a tensor
+ * under the mirror of that axis: the box then evolves exactly like the
+ * periodic box of twice the length holding the box and its mirror image, with
+ * tangential E odd about a PEC wall (even about a PMC wall).  Beside a wall
+ * the ln mu gradient uses the mirrored medium.  The diagnostic sum of
+ * (div_h B)^2 keeps periodic differences. */
+
+/* Faces of `axis` (0..dim-1) become walls of the given kind (or periodic
+ * again).  Pull streaming only (EINVAL for AA: create the handle with
+ * LBEM_STREAM_PULL, since AUTO takes AA for small 3D FP32 and all 3D FP64
+ * boxes); before lbem_set_medium (ESTATE after).  With walls or an absorber
+ * the solver runs single steps. */
+int lbem_set_boundary(lbem_t h, int axis, int kind);
+
+/* Absorbing layer: after every collision the populations of cell x are
+ * multiplied by 1 - sigma[x] (n host doubles in [0,1); EINVAL otherwise).
+ * E and B decay at the same rate, so electric and magnetic losses keep the
+ * ratio eps : mu and the layer is impedance-matched.  NULL removes it.  Pull
+ * streaming only.  The handle copies sigma; synchronises. */
+int lbem_set_absorber(lbem_t h, const double* sigma);
 
 /* Static description of a status code. */
 const char* lbem_strerror(int code);

@@ -61,11 +61,13 @@ __host__ __device__ __forceinline__ void tile_coords(const Geo& g, int b, int& t
 struct Cell {
     int c;
     int xm, xp, ym, yp, zm, zp;
+    unsigned wall;         // bit i: the upstream cell x - c_i lies beyond a wall
 };
 
 __device__ __forceinline__ Cell make_cell(const Geo& g, int x, int y, int z)
 {
     Cell C;
+    C.wall = 0;
     const int row = g.nx * (y + g.ny * z);
     C.c = row + x;
     C.xm = row + (x == 0 ? g.nx - 1 : x - 1);
@@ -88,6 +90,42 @@ __device__ __forceinline__ int shifted(const Cell& C, int i, int sgn)
     if (a == 0) return s > 0 ? C.xp : C.xm;
     if (a == 1) return s > 0 ? C.yp : C.ym;
     return s > 0 ? C.zp : C.zm;
+}
+
+// Non-periodic faces and absorbing layer.  A wall sits half a cell outside the
+// first and last cell of an axis.  A population that would stream in from
+// beyond it is the cell's own outgoing population along the opposite velocity,
+// reflected as a tensor under the mirror of that axis: negated for the pairs
+// that contain the axis at a PEC wall (tangential E odd about the wall), for
+// the other pairs at a PMC wall.  The absorbing layer multiplies a cell's
+// post-collision populations by keep = 1 - sigma(x).
+struct Bound {
+    int kind[3];           // per axis: 0 periodic, 1 PEC wall, 2 PMC wall
+    const void* keep;      // per-cell 1 - sigma (medium precision), or nullptr
+    __host__ __device__ bool walls() const { return (kind[0] | kind[1] | kind[2]) != 0; }
+};
+
+template <int D>
+__device__ __forceinline__ void mark_walls(Cell& C, const Bound& bc, const Geo& g, int x, int y, int z)
+{
+    unsigned w = 0;
+#pragma unroll
+    for (int i = 1; i < Lat<D>::Q; ++i) {
+        const int a = vaxis(D, i);
+        const int v = a == 0 ? x : (a == 1 ? y : z);
+        const int nv = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+        if (bc.kind[a] != 0 && (vsign(D, i) > 0 ? v == 0 : v == nv - 1)) w |= 1u << i;
+    }
+    C.wall = w;
+}
+
+// sign of the reflection of pair p for a population entering along i
+template <int D>
+__device__ __forceinline__ bool wall_negates(const Bound& bc, int i, int p)
+{
+    const int a = vaxis(D, i);
+    const bool in_pair = pair_a(D, p) == a || pair_b(D, p) == a;
+    return (bc.kind[a] == 1) == in_pair;
 }
 
 template <int D, int RM>
@@ -270,10 +308,11 @@ __device__ __forceinline__ bool stage_source(const SrcArgs<T>& s, int b, T* lds)
 // ---------------------------------------------------------------------------
 // plain FP64/FP32 stream-collide
 // ---------------------------------------------------------------------------
-template <int D, typename T, int RM, int WM, int VEC, bool MU>
+template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX>
 __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T* __restrict__ cl2a,
                                                   const T* __restrict__ dlnmu, const Geo g,
-                                                  const SrcArgs<T> s, const T omega, const int tau_half)
+                                                  const SrcArgs<T> s, const T omega, const int tau_half,
+                                                  const Bound bc)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ T lds[P * NT * VEC];
@@ -284,13 +323,20 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
     for (int v = 0; v < VEC; ++v) {
         const int y = t.y0 + v * t.rb;
         if (t.x >= g.nx || y >= g.ny) continue;
-        const Cell C = make_cell(g, t.x, y, t.z);
+        Cell C = make_cell(g, t.x, y, t.z);
+        if (BX && RM == R_PULL) mark_walls<D>(C, bc, g, t.x, y, t.z);
         T f[Q][P];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-                f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+            for (int p = 0; p < P; ++p) {
+                if (BX && RM == R_PULL && ((C.wall >> i) & 1u)) {
+                    const T v = src[(int64_t)(opp(D, i) * P + p) * g.n + C.c];
+                    f[i][p] = wall_negates<D>(bc, i, p) ? -v : v;
+                } else {
+                    f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+                }
+            }
         const T cl2 = cl2a[C.c];
         T rho[P], K[D], Sp[P];
         moments<D, T>(f, rho, K);
@@ -304,6 +350,13 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
         }
         T out[Q][P];
         collide<D, T>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        if (BX && bc.keep) {
+            const T k = ((const T*)bc.keep)[C.c];
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int p = 0; p < P; ++p) out[i][p] *= k;
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i)
 #pragma unroll
@@ -804,11 +857,11 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
         }
 }
 
-template <int D, typename H, bool GH, int RM, int VEC, bool MU>
+template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
-                                                const int tau_half)
+                                                const int tau_half, const Bound bc)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ float lds[P * NT * VEC];
@@ -819,15 +872,22 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
     for (int v = 0; v < VEC; ++v) {
         const int y = t.y0 + v * t.rb;
         if (t.x >= g.nx || y >= g.ny) continue;
-        const Cell C = make_cell(g, t.x, y, t.z);
+        Cell C = make_cell(g, t.x, y, t.z);
+        if (BX && RM == R_PULL) mark_walls<D>(C, bc, g, t.x, y, t.z);
         const float cl2 = cl2a[C.c];
         const float wc0 = 1.f / cl2 - float(D);
         float f[Q][P];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-                f[i][p] = dev_load<D, H, GH>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
+            for (int p = 0; p < P; ++p) {
+                if (BX && RM == R_PULL && ((C.wall >> i) & 1u)) {
+                    const float v = dev_load<D, H, GH>(Min, Din, g.n, opp(D, i), p, C.c, wc0);
+                    f[i][p] = wall_negates<D>(bc, i, p) ? -v : v;
+                } else {
+                    f[i][p] = dev_load<D, H, GH>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
+                }
+            }
         float rho[P], K[D], Sp[P];
         moments<D, float>(f, rho, K);
 #pragma unroll
@@ -840,6 +900,13 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
         }
         float out[Q][P];
         collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        if (BX && bc.keep) {
+            const float k = ((const float*)bc.keep)[C.c];
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int p = 0; p < P; ++p) out[i][p] *= k;
+        }
         dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
     }
 }
@@ -1112,8 +1179,14 @@ template <int D, typename T, int RM>
 struct PlainReader {
     const T* pop;
     int64_t n;
+    Bound bc;
+    static constexpr bool PULL = RM == R_PULL;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double) const
     {
+        if (PULL && ((C.wall >> i) & 1u)) {
+            const double v = (double)pop[(int64_t)(opp(D, i) * Lat<D>::P + p) * n + C.c];
+            return wall_negates<D>(bc, i, p) ? -v : v;
+        }
         return (double)pop[(int64_t)(read_slot<D, RM>(i) * Lat<D>::P + p) * n + read_cell<D, RM>(C, i)];
     }
 };
@@ -1123,9 +1196,15 @@ struct DevReader {
     const float* M;
     const H* Dv;
     int64_t n;
+    Bound bc;
+    static constexpr bool PULL = RM == R_PULL;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double cl2) const
     {
         const float wc0 = 1.f / (float)cl2 - float(D);
+        if (PULL && ((C.wall >> i) & 1u)) {
+            const float v = dev_load<D, H, GH>(M, Dv, n, opp(D, i), p, C.c, wc0);
+            return (double)(wall_negates<D>(bc, i, p) ? -v : v);
+        }
         return (double)dev_load<D, H, GH>(M, Dv, n, i, p, read_cell<D, RM>(C, i), wc0);
     }
 };
@@ -1166,7 +1245,8 @@ __global__ __launch_bounds__(NT) void k_fields(const R rd, const TM* __restrict_
         const int x = c % g1.nx, y = (c / g1.nx) % g1.ny, z = c / (g1.nx * g1.ny);
         Geo g;
         g.nx = g1.nx; g.ny = g1.ny; g.nz = g1.nz;
-        const Cell C = make_cell(g, x, y, z);
+        Cell C = make_cell(g, x, y, z);
+        if (R::PULL && rd.bc.walls()) mark_walls<D>(C, rd.bc, g, x, y, z);
         const double cl2 = (double)cl2a[c];
         double f[Q][P];
 #pragma unroll
@@ -1259,7 +1339,7 @@ __global__ __launch_bounds__(NT) void k_reduce_partials(const double* __restrict
 template <typename TM>
 __global__ __launch_bounds__(NT) void k_medium(const double* __restrict__ eps, const double* __restrict__ mu,
                                                int D, double w0_vac, const Geo1 g1, TM* cl2, double* mu_out,
-                                               TM* dlnmu, int* flag)
+                                               TM* dlnmu, int* flag, const Bound bc)
 {
     const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (c64 >= g1.n) return;
@@ -1276,7 +1356,14 @@ __global__ __launch_bounds__(NT) void k_medium(const double* __restrict__ eps, c
         const int x = c % g1.nx, y = (c / g1.nx) % g1.ny, z = c / (g1.nx * g1.ny);
         Geo g;
         g.nx = g1.nx; g.ny = g1.ny; g.nz = g1.nz;
-        const Cell C = make_cell(g, x, y, z);
+        Cell C = make_cell(g, x, y, z);
+        // beside a wall the medium is mirrored: the missing neighbour is the cell itself
+        if (bc.kind[0] && x == 0) C.xm = c;
+        if (bc.kind[0] && x == g1.nx - 1) C.xp = c;
+        if (bc.kind[1] && y == 0) C.ym = c;
+        if (bc.kind[1] && y == g1.ny - 1) C.yp = c;
+        if (bc.kind[2] && z == 0) C.zm = c;
+        if (bc.kind[2] && z == g1.nz - 1) C.zp = c;
         const double mxp = mu ? mu[C.xp] : 1.0, mxm = mu ? mu[C.xm] : 1.0;
         const double myp = mu ? mu[C.yp] : 1.0, mym = mu ? mu[C.ym] : 1.0;
         dlnmu[c] = (TM)(0.5 * (log(mxp) - log(mxm)));

@@ -138,6 +138,9 @@ struct lbem_s {
     void* zsrc_val;
     int64_t nzsrc;
     // state
+    // non-periodic faces and absorbing layer
+    int bc_kind[3];
+    void* keep;              // handle-owned, medium precision, or nullptr
     int64_t t;
     bool have_medium, have_fields;
     Impl* impl;
@@ -172,12 +175,22 @@ static Geo1 geo1(const lbem_s* h)
 
 static int blocks1(int64_t n) { return (int)((n + NT - 1) / NT); }
 
+static Bound bound_of(const lbem_s* h)
+{
+    Bound b;
+    for (int a = 0; a < 3; ++a) b.kind[a] = h->bc_kind[a];
+    b.keep = h->keep;
+    return b;
+}
+// walls or an absorber: the single-step kernels with boundary handling
+static bool has_bx(const lbem_s* h) { return h->keep != nullptr || bound_of(h).walls(); }
+
 template <int D, typename TM>
 static hipError_t launch_medium(lbem_s* h, const double* deps, const double* dmu, int* dflag)
 {
     hipLaunchKernelGGL((k_medium<TM>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, deps, dmu, D,
                        h->cfg.w0_vac, geo1(h), (TM*)h->cl2, h->cfg.mu_varies ? h->mu_r : nullptr,
-                       (TM*)h->dlnmu, dflag);
+                       (TM*)h->dlnmu, dflag, bound_of(h));
     return hipGetLastError();
 }
 
@@ -259,12 +272,12 @@ static hipError_t go_fused3(lbem_s* h, const T* src, T* dst, const double* amp)
 
 static bool fused_ok(const lbem_s* h)
 {
-    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1;
+    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1 && !has_bx(h);
 }
 
 template <int D, typename T>
 struct PlainImpl : Impl {
-    template <int RM, int WM, int V, bool MU>
+    template <int RM, int WM, int V, bool MU, bool BX = false>
     static hipError_t go(lbem_s* h, const T* src, T* dst, T amp)
     {
         SrcArgs<T> s;
@@ -273,14 +286,20 @@ struct PlainImpl : Impl {
         s.val = (const T*)h->src_val;
         s.amp = amp;
         const double om = 1.0 / h->cfg.tau;
-        hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
-                           src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
-                           (int)(h->cfg.tau == 0.5));
+        hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
+                           h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
+                           (int)(h->cfg.tau == 0.5), bound_of(h));
         return hipGetLastError();
     }
     template <int RM, int WM>
     static hipError_t go_v(lbem_s* h, const T* src, T* dst, T amp)
     {
+        if constexpr (WM == W_LOCAL && RM != R_PULL_SWAP) {
+            if (has_bx(h)) {   // pull streaming only (AA is refused with walls or an absorber)
+                if (h->mu_set) return go<RM, WM, 1, true, true>(h, src, dst, amp);
+                return go<RM, WM, 1, false, true>(h, src, dst, amp);
+            }
+        }
         if (h->mu_set) return go<RM, WM, 1, true>(h, src, dst, amp);
         switch (h->vec) {
             case 2: return go<RM, WM, 2, false>(h, src, dst, amp);
@@ -324,10 +343,12 @@ struct PlainImpl : Impl {
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         const T* a = (const T*)h->pop[h->cur];
-        if (h->layout == LAYOUT_NATURAL) return launch_fields<D, T>(h, PlainReader<D, T, R_LOCAL>{a, h->n}, E, B, partials);
+        const Bound bc = bound_of(h);
+        if (h->layout == LAYOUT_NATURAL)
+            return launch_fields<D, T>(h, PlainReader<D, T, R_LOCAL>{a, h->n, bc}, E, B, partials);
         if (h->layout == LAYOUT_PULL_PENDING)
-            return launch_fields<D, T>(h, PlainReader<D, T, R_PULL>{a, h->n}, E, B, partials);
-        return launch_fields<D, T>(h, PlainReader<D, T, R_PULL_SWAP>{a, h->n}, E, B, partials);
+            return launch_fields<D, T>(h, PlainReader<D, T, R_PULL>{a, h->n, bc}, E, B, partials);
+        return launch_fields<D, T>(h, PlainReader<D, T, R_PULL_SWAP>{a, h->n, bc}, E, B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
     {
@@ -351,11 +372,11 @@ struct DevImpl : Impl {
         const int P = Lat<D>::P;
         return (H*)(h->pop[k] + align256((size_t)(P + D) * h->n * 4));
     }
-    template <int RM, int V, bool MU>
+    template <int RM, int V, bool MU, bool BX = false>
     static hipError_t go(lbem_s* h, int from, int to, float amp)
     {
         SrcArgs<float> s;
-        if constexpr (D == 3) {
+        if constexpr (D == 3 && !BX) {
             if (h->zmarch) {
                 s.off = h->nzsrc ? h->zsrc_off : nullptr;
                 s.ent = h->zsrc_ent;
@@ -372,15 +393,19 @@ struct DevImpl : Impl {
         s.ent = h->src_ent;
         s.val = (const float*)h->src_val;
         s.amp = amp;
-        hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU>), dim3(h->geo.nblocks), dim3(NT), 0, h->stream,
-                           M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+        hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
+                           h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
-                           (int)(h->cfg.tau == 0.5));
+                           (int)(h->cfg.tau == 0.5), bound_of(h));
         return hipGetLastError();
     }
     template <int RM>
     static hipError_t go_v(lbem_s* h, int from, int to, float amp)
     {
+        if (has_bx(h)) {
+            if (h->mu_set) return go<RM, 1, true, true>(h, from, to, amp);
+            return go<RM, 1, false, true>(h, from, to, amp);
+        }
         if (h->mu_set) return go<RM, 1, true>(h, from, to, amp);
         switch (h->vec) {
             case 2: return go<RM, 2, false>(h, from, to, amp);
@@ -401,9 +426,11 @@ struct DevImpl : Impl {
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         if (h->layout == LAYOUT_NATURAL)
-            return launch_fields<D, float>(h, DevReader<D, H, GH, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n},
+            return launch_fields<D, float>(h, DevReader<D, H, GH, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n,
+                                                                            bound_of(h)},
                                            E, B, partials);
-        return launch_fields<D, float>(h, DevReader<D, H, GH, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n}, E,
+        return launch_fields<D, float>(h, DevReader<D, H, GH, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n,
+                                                                       bound_of(h)}, E,
                                        B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
@@ -796,6 +823,7 @@ int lbem_destroy(lbem_t h)
     if (!h) return LBEM_OK;
     (void)hipStreamSynchronize(h->stream);
     free_source(h);
+    if (h->keep) (void)hipFree(h->keep);
     if (h->partials) (void)hipFree(h->partials);
     if (h->own_mem && h->arena) (void)hipFree(h->arena);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
@@ -863,6 +891,46 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B)
     if (e != hipSuccess) return LBEM_EDEVICE;
     h->t = 0;
     h->have_fields = true;
+    return LBEM_OK;
+}
+
+int lbem_set_boundary(lbem_t h, int axis, int kind)
+{
+    if (!h || axis < 0 || axis >= h->D || kind < LBEM_BC_PERIODIC || kind > LBEM_BC_PMC) return LBEM_EINVAL;
+    if (kind != LBEM_BC_PERIODIC && h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+    if (h->have_medium) return LBEM_ESTATE;
+    h->bc_kind[axis] = kind;
+    return LBEM_OK;
+}
+
+int lbem_set_absorber(lbem_t h, const double* sigma)
+{
+    if (!h) return LBEM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
+    if (!sigma) {
+        if (h->keep) (void)hipFree(h->keep);
+        h->keep = nullptr;
+        return LBEM_OK;
+    }
+    if (h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+    const int64_t n = h->n;
+    for (int64_t c = 0; c < n; ++c)
+        if (!(sigma[c] >= 0.0 && sigma[c] < 1.0)) return LBEM_EINVAL;
+    const bool f64 = h->prec == LBEM_F64;
+    const size_t tm = f64 ? 8 : 4;
+    std::vector<char> host((size_t)n * tm);
+    for (int64_t c = 0; c < n; ++c) {
+        const double k = 1.0 - sigma[c];
+        if (f64) ((double*)host.data())[c] = k;
+        else ((float*)host.data())[c] = (float)k;
+    }
+    if (!h->keep && hipMalloc(&h->keep, (size_t)n * tm) != hipSuccess) {
+        h->keep = nullptr;
+        return LBEM_ENOMEM;
+    }
+    if (hipMemcpyAsync(h->keep, host.data(), (size_t)n * tm, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return LBEM_EDEVICE;
     return LBEM_OK;
 }
 
@@ -1261,6 +1329,7 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         if (!h || nsteps[i] < 0 || nsteps[i] > b->ksteps) return LBEM_EINVAL;
         if (h->nsrc != 0 || h->mu_set || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
         if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate kernels
+        if (has_bx(h)) return LBEM_EINVAL;                // periodic boxes only
         if (!h->have_fields) return LBEM_ESTATE;
         for (int j = 0; j < i; ++j)
             if (handles[j] == h) return LBEM_EINVAL;

@@ -24,7 +24,9 @@ STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_medium",
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
            "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
-           "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state")
+           "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state",
+           "lbem_set_boundary", "lbem_set_absorber")
+BOUNDARY = {"periodic": 0, "pec": 1, "pmc": 2}
 
 
 class Config(C.Structure):
@@ -70,6 +72,8 @@ def load():
     L.lbem_state_bytes.restype = C.c_size_t
     L.lbem_get_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
     L.lbem_set_state.argtypes = [vp, vp, C.c_size_t, C.c_int]
+    L.lbem_set_boundary.argtypes = [vp, C.c_int, C.c_int]
+    L.lbem_set_absorber.argtypes = [vp, vp]
     L.lbem_strerror.argtypes = [C.c_int]
     L.lbem_strerror.restype = C.c_char_p
     _lib = L
@@ -173,6 +177,16 @@ class Solver:
         e = _f64(E, 3 * self.n)
         b = _f64(B, 3 * self.n)
         self._chk(load().lbem_init_fields(self._h, _ptr(e), _ptr(b)), "lbem_init_fields")
+
+    def set_boundary(self, axis: int, kind: str):
+        """Walls on both faces of ``axis``: 'pec', 'pmc' or 'periodic' (before
+        set_medium)."""
+        self._chk(load().lbem_set_boundary(self._h, int(axis), BOUNDARY[kind]), "lbem_set_boundary")
+
+    def set_absorber(self, sigma=None):
+        """Absorbing layer sigma(x) in [0,1) per cell; None removes it."""
+        s = None if sigma is None else _f64(sigma, self.n)
+        self._chk(load().lbem_set_absorber(self._h, _ptr(s)), "lbem_set_absorber")
 
     def set_source(self, comp, cells, weights):
         c = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1)

@@ -1,0 +1,179 @@
+"""Non-periodic faces (PEC / PMC walls) and the absorbing layer on the GPU,
+through the C ABI, against the oracle on the same seeded inputs (every term:
+heterogeneous eps and mu, scattered current source), plus the physics the
+walls and the layer must show at a larger size."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, random_problem, rel
+from oracle import oracle as O
+from paper_1108_2651_amd import inputs, lbem
+from test_gpu_parity import TOL, energy_norm_error
+
+pytestmark = pytest.mark.gpu
+
+
+def layer(shape, width, smax, axes):
+    """sigma rising quadratically over `width` cells at both faces of each axis."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sig = np.zeros(shape[::-1])
+    for a, v in zip((0, 1, 2), (x, y, z)):
+        if a not in axes:
+            continue
+        n = shape[a]
+        d = np.minimum(v, n - 1 - v).astype(float)
+        sig = np.maximum(sig, np.where(d < width, smax * ((width - d - 0.5) / width) ** 2, 0.0))
+    return sig.ravel()
+
+
+def setup_both(p, prec, walls, sigma):
+    s = lbem.Solver(p.dim, p.shape, prec, w0_vac=p.w0_vac, mu_varies=p.mu_r is not None, streaming="pull")
+    o = O.Oracle(p.dim, p.shape, p.tau, p.w0_vac)
+    for a, k in walls:
+        s.set_boundary(a, k)
+        o.set_boundary(a, k)
+    s.set_medium(p.eps_r, p.mu_r)
+    o.set_medium(p.eps_r, p.mu_r)
+    if sigma is not None:
+        s.set_absorber(sigma)
+        o.set_absorber(sigma)
+    s.init_fields(p.E0, p.B0)
+    o.init_fields(p.E0, p.B0)
+    if len(p.src_cells):
+        s.set_source(p.src_comp, p.src_cells, p.src_weights)
+        o.set_source(p.src_comp, p.src_cells, p.src_weights)
+    return s, o
+
+
+CASES = [(2, (70, 33, 1), [(0, "pec")], False, True), (2, (64, 40, 1), [(0, "pmc"), (1, "pec")], True, True),
+         (2, (1, 50, 1), [(1, "pec")], True, False), (3, (19, 13, 11), [(2, "pec")], True, True),
+         (3, (16, 12, 10), [(0, "pmc"), (1, "pmc"), (2, "pec")], False, True),
+         (3, (20, 9, 7), [(0, "pec"), (1, "pec")], True, False)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev", "f16ghost"])
+@pytest.mark.parametrize("dim,shape,walls,mu,absorb", CASES)
+def test_walls_and_absorber_match_oracle(dim, shape, walls, mu, absorb, prec):
+    steps = 57
+    p = random_problem(dim, shape, seed=sum(shape) + len(walls), mu=mu, nsteps=steps)
+    sigma = layer(shape, 4, 0.08, [a for a, _ in walls]) if absorb else None
+    s, o = setup_both(p, prec, walls, sigma)
+    assert s.steps_per_launch == 1
+    s.step(steps, p.amp[:steps])
+    o.step(steps, p.amp[:steps])
+    (Eg, Bg), (Eo, Bo) = s.moments(), o.fields()
+    eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+    eN = energy_norm_error(Eg, Bg, Eo, Bo, o, p.mu_r)
+    announce(f"walls {dim}D {shape} {walls} mu={mu} absorber={absorb} {prec}: E {eE:.2e} B {eB:.2e} energy {eN:.2e}")
+    if prec in ("f64", "f32"):
+        t = TOL[prec]
+        assert eE <= t and eB <= t, (eE, eB)
+        dg, do = s.energy(), o.diag()
+        for k in ("energy", "qc", "divb2", "b2"):
+            assert abs(dg[k] - do[k]) <= (1e-11 if prec == "f64" else 2e-5) * max(abs(do[k]), 1e-300), k
+    else:
+        tol = 5e-3     # white-noise fields: the 16-bit codes carry O(1) of each population
+        assert eN <= tol and eE <= 2 * tol and eB <= 2 * tol, (eN, eE, eB)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_pec_box_is_its_mirror_image(prec):
+    """GPU walled box vs the GPU periodic doubled box with mirror-image fields."""
+    nx, ny, nz = 48, 20, 12
+    rng = np.random.default_rng(5)
+    n = nx * ny * nz
+    eps = rng.uniform(1, 4, n)
+    E = rng.standard_normal((3, n))
+    B = rng.standard_normal((3, n))
+    a = lbem.Solver(3, (nx, ny, nz), prec, streaming="pull")
+    a.set_boundary(0, "pec")
+    a.set_medium(eps)
+    a.init_fields(E, B)
+    a.step(150)
+    Ew, Bw = a.moments()
+
+    def mir(f, sign):
+        f4 = f.reshape(3, nz, ny, nx)
+        return np.concatenate([f4, np.flip(f4, axis=3) * np.asarray(sign)[:, None, None, None]], axis=3)
+
+    e2 = np.concatenate([eps.reshape(nz, ny, nx), np.flip(eps.reshape(nz, ny, nx), axis=2)], axis=2)
+    b = lbem.Solver(3, (2 * nx, ny, nz), prec, streaming="pull")
+    b.set_medium(e2.ravel())
+    b.init_fields(mir(E, [1, -1, -1]).reshape(3, -1), mir(B, [-1, 1, 1]).reshape(3, -1))
+    b.step(150)
+    Ep, Bp = b.moments()
+    Ep = Ep.reshape(3, nz, ny, 2 * nx)[..., :nx].reshape(3, -1)
+    Bp = Bp.reshape(3, nz, ny, 2 * nx)[..., :nx].reshape(3, -1)
+    t = 1e-13 if prec == "f64" else 2e-6
+    assert rel(Ew, Ep) <= t and rel(Bw, Bp) <= t, (rel(Ew, Ep), rel(Bw, Bp))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16ghost"])
+def test_graded_layer_absorbs_on_gpu(prec):
+    nx, ny = 1200, 16
+    x = np.tile(np.arange(nx), ny)
+    cv = inputs.vacuum_speed(2, 1.0 / 3.0)
+    f = np.exp(-(x - 300.0) ** 2 / (2 * 12.0 ** 2))
+    E = np.zeros((3, nx * ny))
+    B = np.zeros((3, nx * ny))
+    E[2] = f
+    B[1] = -f / cv
+    x0, L = nx - 100, 100.0
+    sigma = np.where(x >= x0, 0.08 * ((x - x0 + 0.5) / L) ** 2, 0.0)
+    res = {}
+    for name, sg in (("wall", None), ("layer", sigma)):
+        s = lbem.Solver(2, (nx, ny, 1), prec, streaming="pull")
+        s.set_boundary(0, "pec")
+        s.set_medium(np.ones(nx * ny))
+        if sg is not None:
+            s.set_absorber(sg)
+        s.init_fields(E, B)
+        e0 = s.energy()["energy"]
+        s.step(int(2 * (nx - 300) / cv))
+        Ef, Bf = s.moments()
+        ea = 1.0 / (cv * cv)
+        dens = ea * (Ef ** 2).sum(0) + (Bf ** 2).sum(0)
+        res[name] = (dens[x < x0].sum() / e0, s.energy()["energy"] / e0)
+        s.close()
+    announce(f"graded layer {prec}: wall returns {res['wall'][0]:.3f}, layer returns {res['layer'][0]:.2e}, "
+             f"keeps {res['layer'][1]:.2e}")
+    assert res["wall"][0] > 0.9
+    assert res["layer"][0] < 1e-3 and res["layer"][1] < 2e-3
+
+
+def test_boundary_call_rules():
+    s = lbem.Solver(2, (16, 8, 1), "f32", streaming="aa")
+    with pytest.raises(lbem.LbemError) as e:
+        s.set_boundary(0, "pec")                 # walls need pull streaming
+    assert e.value.code == lbem.LBEM_EINVAL
+    with pytest.raises(lbem.LbemError) as e:
+        s.set_absorber(np.zeros(s.n))
+    assert e.value.code == lbem.LBEM_EINVAL
+    s.close()
+    s = lbem.Solver(3, (8, 8, 8), "f32", streaming="pull")
+    with pytest.raises(lbem.LbemError) as e:
+        s.set_boundary(3, "pec")                 # no such axis
+    assert e.value.code == lbem.LBEM_EINVAL
+    s.set_medium(np.ones(s.n))
+    with pytest.raises(lbem.LbemError) as e:
+        s.set_boundary(0, "pec")                 # after the medium
+    assert e.value.code == lbem.LBEM_ESTATE
+    bad = np.zeros(s.n)
+    bad[3] = 1.0
+    with pytest.raises(lbem.LbemError) as e:
+        s.set_absorber(bad)                      # sigma must lie in [0,1)
+    assert e.value.code == lbem.LBEM_EINVAL
+    s.set_absorber(np.full(s.n, 0.01))
+    s.init_fields(np.zeros((3, s.n)), np.ones((3, s.n)))
+    st = __import__("torch").cuda.Stream()
+    from paper_1108_2651_amd import serve
+    b = serve.Batch(2, 4, st)
+    with pytest.raises(lbem.LbemError) as e:
+        b.run([s], [1])                          # batches hold periodic boxes only
+    assert e.value.code == lbem.LBEM_EINVAL
+    b.close()
+    s.set_absorber(None)
+    s.step(3)
+    s.close()
