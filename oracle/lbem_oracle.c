@@ -49,6 +49,21 @@
  *    multiplied by 1 - sigma(x); E and B decay at the same rate, so the
  *    layer's electric and magnetic losses stay in the ratio eps : mu (an
  *    impedance-matched absorber).
+ *  - Frequency-dispersive permittivity (the convolution term of the source,
+ *    which the paper defers to auxiliary differential equations): one
+ *    Lorentz pole per cell, chi(w) = wp2 / (w02 - w^2 - i gamma w), relative
+ *    to the cell's permittivity, in lattice units.  Auxiliary fields P (the
+ *    polarisation in units of E) at integer times and J = dP/dt at half
+ *    times: J(t+1/2) = [(1 - gamma/2) J(t-1/2) + wp2 E(t) - w02 P(t)] /
+ *    (1 + gamma/2), P(t+1) = P(t) + J(t+1/2).  The polarisation source of
+ *    step t, which the scheme integrates over [t, t+1], is -J(t+1/2)
+ *    (leapfrog: E at integer, J at half-integer times).  It enters the rest
+ *    particle only, T_{0,a,b} = -(1/c^2) eps_{g a b} S_g: the same change of
+ *    E and no first moment, but unlike the w_i-weighted injection (which adds
+ *    (c^2/2) times the lattice Laplacian of S(t) alone to the three-level form
+ *    of the update) it enters as S(t) - S(t-1), so the coupled update is the
+ *    centred leapfrog of E'' = c^2 lap E - P'' and stays stable; the
+ *    w_i-weighted form pumps one polariton branch.  P and J start at zero.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
  */
@@ -79,6 +94,8 @@ typedef struct {
     double *g, *gs;       /* [n][Q][D][D] populations, streamed copy */
     double *jd;           /* [3][n] current-density footprint (weights) */
     double *keep;         /* [n] 1 - sigma of the absorbing layer, or NULL */
+    double *ade;          /* [3][n] wp2, w02, gamma of the Lorentz pole, or NULL */
+    double *pol, *pcur;   /* [3][n] P and J (per field component) */
     int bc[3];            /* per axis: 0 periodic, 1 PEC wall, 2 PMC wall */
     long t;
     int have_medium, have_fields, has_mu;
@@ -245,7 +262,12 @@ orc_t* orc_create(int D, long nx, long ny, long nz, double tau, double w0_vac)
 
 void orc_destroy(orc_t* o)
 {
-    if (o) free(o->keep);
+    if (o) {
+        free(o->keep);
+        free(o->ade);
+        free(o->pol);
+        free(o->pcur);
+    }
     if (!o) return;
     free(o->cL2); free(o->w0); free(o->eps_abs); free(o->mu_r); free(o->dlnmu);
     free(o->g); free(o->gs); free(o->jd); free(o);
@@ -309,6 +331,10 @@ int orc_init_fields(orc_t* o, const double* E, const double* B)
     }
     o->t = 0;
     o->have_fields = 1;
+    if (o->ade) {
+        memset(o->pol, 0, sizeof(double) * 3 * n);
+        memset(o->pcur, 0, sizeof(double) * 3 * n);
+    }
     return ORC_OK;
 }
 
@@ -345,7 +371,7 @@ int orc_step(orc_t* o, long nsteps, const double* amp)
         double a = amp ? amp[s] : 0.0;
 #pragma omp parallel for schedule(static)
         for (long x = 0; x < n; ++x) {
-            double E[3], B[3], S[3], out[63];
+            double E[3], B[3], S[3], Sp[3] = {0.0, 0.0, 0.0}, out[63];
             cell_fields(o, x, E, B);
             double cM2 = o->cL2[x] / (double)(D - 1);
             for (int gm = 0; gm < 3; ++gm) {
@@ -356,7 +382,24 @@ int orc_step(orc_t* o, long nsteps, const double* amp)
                             mu_term += levi(gm, b, k) * B[b] * o->dlnmu[k * n + x];
                 S[gm] = cM2 * mu_term - a * o->jd[gm * n + x] / o->eps_abs[x];
             }
+            if (o->ade) {
+                double wp2 = o->ade[x], w02 = o->ade[n + x], gam = o->ade[2 * n + x];
+                for (int gm = 0; gm < 3; ++gm) {
+                    double Jo = o->pcur[gm * n + x], Po = o->pol[gm * n + x];
+                    double Jn = ((1.0 - 0.5 * gam) * Jo + wp2 * E[gm] - w02 * Po) / (1.0 + 0.5 * gam);
+                    Sp[gm] = -Jn;
+                    o->pcur[gm * n + x] = Jn;
+                    o->pol[gm * n + x] = Po + Jn;
+                }
+            }
             collide_cell(D, o->c, o->w0[x], o->cL2[x], o->tau, &o->g[GI(o, x, 0, 0, 0)], S, out);
+            if (o->ade)   /* polarisation source: rest particle only */
+                for (int a2 = 0; a2 < D; ++a2)
+                    for (int b2 = 0; b2 < D; ++b2) {
+                        double es = 0.0;
+                        for (int gm = 0; gm < 3; ++gm) es += levi(gm, a2, b2) * Sp[gm];
+                        out[a2 * D + b2] += -es / o->cL2[x];
+                    }
             if (o->keep)
                 for (int k = 0; k < Q * D * D; ++k) out[k] *= o->keep[x];
             /* streaming, eq. STREAM: g(x + c_i, t+1) = g'(x, t); through a wall
@@ -397,6 +440,46 @@ int orc_set_boundary(orc_t* o, int axis, int kind)
     if (axis < 0 || axis >= o->D || kind < 0 || kind > 2) return ORC_EINVAL;
     if (o->have_medium) return ORC_ESTATE;
     o->bc[axis] = kind;
+    return ORC_OK;
+}
+
+/* One Lorentz pole per cell (wp2, w02, gamma >= 0; wp2 == NULL removes the
+ * dispersion); the auxiliary fields restart from zero. */
+int orc_set_dispersion(orc_t* o, const double* wp2, const double* w02, const double* gamma)
+{
+    long n = o->n;
+    if (!wp2) {
+        free(o->ade); free(o->pol); free(o->pcur);
+        o->ade = o->pol = o->pcur = NULL;
+        return ORC_OK;
+    }
+    for (long x = 0; x < n; ++x) {
+        double a = wp2[x], b = w02 ? w02[x] : 0.0, g = gamma ? gamma[x] : 0.0;
+        if (!(a >= 0.0) || !(b >= 0.0) || !(g >= 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(g))
+            return ORC_EINVAL;
+    }
+    if (!o->ade) {
+        o->ade = (double*)malloc(sizeof(double) * 3 * n);
+        o->pol = (double*)calloc(3 * n, sizeof(double));
+        o->pcur = (double*)calloc(3 * n, sizeof(double));
+        if (!o->ade || !o->pol || !o->pcur) return ORC_ENOMEM;
+    }
+    for (long x = 0; x < n; ++x) {
+        o->ade[x] = wp2[x];
+        o->ade[n + x] = w02 ? w02[x] : 0.0;
+        o->ade[2 * n + x] = gamma ? gamma[x] : 0.0;
+    }
+    memset(o->pol, 0, sizeof(double) * 3 * n);
+    memset(o->pcur, 0, sizeof(double) * 3 * n);
+    return ORC_OK;
+}
+
+/* Auxiliary fields P and J of the dispersion, component-major [3][n]. */
+int orc_polarisation(const orc_t* o, double* P, double* J)
+{
+    if (!o->ade) return ORC_ESTATE;
+    memcpy(P, o->pol, sizeof(double) * 3 * o->n);
+    memcpy(J, o->pcur, sizeof(double) * 3 * o->n);
     return ORC_OK;
 }
 

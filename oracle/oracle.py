@@ -52,6 +52,8 @@ def lib():
         L.orc_velocities.argtypes = [C.c_int, np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")]
         L.orc_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_set_absorber.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_set_dispersion.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_polarisation.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
 
@@ -136,6 +138,24 @@ class Oracle:
         else:
             s = np.ascontiguousarray(sigma, np.float64).ravel()
             _chk(lib().orc_set_absorber(self._h, s.ctypes.data_as(C.c_void_p)))
+
+    def set_dispersion(self, wp2=None, w02=None, gamma=None):
+        """One Lorentz pole per cell, chi(w) = wp2/(w02 - w^2 - i gamma w)
+        relative to the cell's permittivity (lattice units); wp2=None removes
+        it.  Scalars broadcast over the cells."""
+        if wp2 is None:
+            _chk(lib().orc_set_dispersion(self._h, None, None, None))
+            return
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64), (self.n,)))
+                for v in (wp2, 0.0 if w02 is None else w02, 0.0 if gamma is None else gamma)]
+        self._disp = arrs
+        _chk(lib().orc_set_dispersion(self._h, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+
+    def polarisation(self):
+        P = np.zeros((3, self.n))
+        J = np.zeros((3, self.n))
+        _chk(lib().orc_polarisation(self._h, P.reshape(-1), J.reshape(-1)))
+        return P, J
 
     def init_fields(self, E, B):
         _chk(lib().orc_init_fields(self._h, np.ascontiguousarray(E, np.float64).reshape(-1),
