@@ -205,6 +205,24 @@ int lbem_set_boundary(lbem_t h, int axis, int kind);
  * streaming only.  The handle copies sigma; synchronises. */
 int lbem_set_absorber(lbem_t h, const double* sigma);
 
+/* ---- frequency-dispersive permittivity ----
+ * The convolution term of the Maxwell source (Section "The Maxwell
+ * Equations"), which the paper leaves to auxiliary differential equations:
+ * one Lorentz pole per cell, chi(w) = wp2 / (w02 - w^2 - i gamma w) relative
+ * to the cell's permittivity, in lattice units (time step 1).  Auxiliary
+ * fields P (polarisation in units of E) at integer and J = dP/dt at
+ * half-integer times: J(t+1/2) = [(1-gamma/2) J(t-1/2) + wp2 E(t) - w02 P(t)]
+ * / (1+gamma/2), P(t+1) = P(t) + J(t+1/2); the source -J(t+1/2) of step t
+ * enters the rest particle only (the w_i-weighted form of the other sources
+ * filters S(t) but not S(t-1) and would pump one polariton branch).
+ * wp2: n host doubles >= 0 (NULL removes the dispersion); w02, gamma: n
+ * doubles >= 0 or NULL for zeros (Drude, lossless).  EINVAL on negative or
+ * non-finite values or AA streaming.  P and J restart from zero here and at
+ * lbem_init_fields; they are part of the checkpoint blob.  Stability of
+ * large wp2 or w02 is the caller's (lattice units: keep them well below 1).
+ * Synchronises; the solver then runs single steps. */
+int lbem_set_dispersion(lbem_t h, const double* wp2, const double* w02, const double* gamma);
+
 /* Static description of a status code. */
 const char* lbem_strerror(int code);
 

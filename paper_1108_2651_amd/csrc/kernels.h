@@ -92,21 +92,49 @@ __device__ __forceinline__ int shifted(const Cell& C, int i, int sgn)
     return s > 0 ? C.zp : C.zm;
 }
 
-// Non-periodic faces and absorbing layer.  A wall sits half a cell outside the
-// first and last cell of an axis.  A population that would stream in from
-// beyond it is the cell's own outgoing population along the opposite velocity,
-// reflected as a tensor under the mirror of that axis: negated for the pairs
-// that contain the axis at a PEC wall (tangential E odd about the wall), for
-// the other pairs at a PMC wall.  The absorbing layer multiplies a cell's
-// post-collision populations by keep = 1 - sigma(x).
-struct Bound {
+// Cell-local extras of the single-step pull kernels.
+// Walls: a wall sits half a cell outside the first and last cell of an axis.
+// A population that would stream in from beyond it is the cell's own outgoing
+// population along the opposite velocity, reflected as a tensor under the
+// mirror of that axis: negated for the pairs that contain the axis at a PEC
+// wall (tangential E odd about the wall), for the other pairs at a PMC wall.
+// Absorbing layer: a cell's post-collision populations times keep = 1 - sigma.
+// Dispersion: one Lorentz pole per cell (the convolution term of the Maxwell
+// source by an auxiliary differential equation).  Per pair p, with E_p =
+// sgn(p) E_gamma(p) = -Lambda_p: J(t+1/2) = c1 J(t-1/2) + c2 E_p(t) - c3 P(t),
+// P(t+1) = P(t) + J(t+1/2) (c1 = (1-g/2)/(1+g/2), c2 = wp2/(1+g/2),
+// c3 = w02/(1+g/2)); the source -J(t+1/2) enters the rest particle only,
+// T_0p = J(t+1/2)/c^2, which keeps the coupled update a centred leapfrog.
+struct CellExt {
     int kind[3];           // per axis: 0 periodic, 1 PEC wall, 2 PMC wall
     const void* keep;      // per-cell 1 - sigma (medium precision), or nullptr
+    const void* ade;       // [3][n] c1, c2, c3 (medium precision), or nullptr
+    void* pol;             // [2P][n] P_p then J_p, updated in place by the cell's thread
     __host__ __device__ bool walls() const { return (kind[0] | kind[1] | kind[2]) != 0; }
 };
 
+// the dispersion update of one cell: new J per pair (the caller adds J/c^2 to
+// the rest particle after collision)
+template <int D, typename T>
+__device__ __forceinline__ void ade_update(const CellExt& bc, int64_t n, int c, T cl2, const T (&rho)[Lat<D>::P],
+                                           T (&Jn)[Lat<D>::P])
+{
+    constexpr int P = Lat<D>::P;
+    const T* co = (const T*)bc.ade;
+    T* st = (T*)bc.pol;
+    const T c1 = co[c], c2 = co[n + c], c3 = co[2 * n + c];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const T Po = st[(int64_t)p * n + c], Jo = st[(int64_t)(P + p) * n + c];
+        const T J = c1 * Jo - c2 * (cl2 * rho[p]) - c3 * Po;
+        Jn[p] = J;
+        st[(int64_t)p * n + c] = Po + J;
+        st[(int64_t)(P + p) * n + c] = J;
+    }
+}
+
 template <int D>
-__device__ __forceinline__ void mark_walls(Cell& C, const Bound& bc, const Geo& g, int x, int y, int z)
+__device__ __forceinline__ void mark_walls(Cell& C, const CellExt& bc, const Geo& g, int x, int y, int z)
 {
     unsigned w = 0;
 #pragma unroll
@@ -121,7 +149,7 @@ __device__ __forceinline__ void mark_walls(Cell& C, const Bound& bc, const Geo& 
 
 // sign of the reflection of pair p for a population entering along i
 template <int D>
-__device__ __forceinline__ bool wall_negates(const Bound& bc, int i, int p)
+__device__ __forceinline__ bool wall_negates(const CellExt& bc, int i, int p)
 {
     const int a = vaxis(D, i);
     const bool in_pair = pair_a(D, p) == a || pair_b(D, p) == a;
@@ -312,7 +340,7 @@ template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX>
 __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T* __restrict__ cl2a,
                                                   const T* __restrict__ dlnmu, const Geo g,
                                                   const SrcArgs<T> s, const T omega, const int tau_half,
-                                                  const Bound bc)
+                                                  const CellExt bc)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ T lds[P * NT * VEC];
@@ -348,8 +376,15 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
             for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
             add_mu_source<D, T>(K, cl2, dl, Sp);
         }
+        T Jn[P];
+        const bool ade = BX && bc.ade != nullptr;
+        if (ade) ade_update<D, T>(bc, g.n, C.c, cl2, rho, Jn);
         T out[Q][P];
         collide<D, T>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        if (ade) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
+        }
         if (BX && bc.keep) {
             const T k = ((const T*)bc.keep)[C.c];
 #pragma unroll
@@ -861,7 +896,7 @@ template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
-                                                const int tau_half, const Bound bc)
+                                                const int tau_half, const CellExt bc)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ float lds[P * NT * VEC];
@@ -898,8 +933,15 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
             for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
             add_mu_source<D, float>(K, cl2, dl, Sp);
         }
+        float Jn[P];
+        const bool ade = BX && bc.ade != nullptr;
+        if (ade) ade_update<D, float>(bc, g.n, C.c, cl2, rho, Jn);
         float out[Q][P];
         collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        if (ade) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
+        }
         if (BX && bc.keep) {
             const float k = ((const float*)bc.keep)[C.c];
 #pragma unroll
@@ -1179,7 +1221,7 @@ template <int D, typename T, int RM>
 struct PlainReader {
     const T* pop;
     int64_t n;
-    Bound bc;
+    CellExt bc;
     static constexpr bool PULL = RM == R_PULL;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double) const
     {
@@ -1196,7 +1238,7 @@ struct DevReader {
     const float* M;
     const H* Dv;
     int64_t n;
-    Bound bc;
+    CellExt bc;
     static constexpr bool PULL = RM == R_PULL;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double cl2) const
     {
@@ -1339,7 +1381,7 @@ __global__ __launch_bounds__(NT) void k_reduce_partials(const double* __restrict
 template <typename TM>
 __global__ __launch_bounds__(NT) void k_medium(const double* __restrict__ eps, const double* __restrict__ mu,
                                                int D, double w0_vac, const Geo1 g1, TM* cl2, double* mu_out,
-                                               TM* dlnmu, int* flag, const Bound bc)
+                                               TM* dlnmu, int* flag, const CellExt bc)
 {
     const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (c64 >= g1.n) return;

@@ -141,6 +141,9 @@ struct lbem_s {
     // non-periodic faces and absorbing layer
     int bc_kind[3];
     void* keep;              // handle-owned, medium precision, or nullptr
+    // frequency-dispersive permittivity (one Lorentz pole per cell)
+    void* ade;               // [3][n] coefficients, handle-owned, or nullptr
+    void* pol;               // [2P][n] auxiliary P and J per pair
     int64_t t;
     bool have_medium, have_fields;
     Impl* impl;
@@ -175,22 +178,26 @@ static Geo1 geo1(const lbem_s* h)
 
 static int blocks1(int64_t n) { return (int)((n + NT - 1) / NT); }
 
-static Bound bound_of(const lbem_s* h)
+static CellExt ext_of(const lbem_s* h)
 {
-    Bound b;
+    CellExt b;
     for (int a = 0; a < 3; ++a) b.kind[a] = h->bc_kind[a];
     b.keep = h->keep;
+    b.ade = h->ade;
+    b.pol = h->pol;
     return b;
 }
-// walls or an absorber: the single-step kernels with boundary handling
-static bool has_bx(const lbem_s* h) { return h->keep != nullptr || bound_of(h).walls(); }
+// walls, an absorber or dispersion: the single-step kernels with cell extras
+static bool has_bx(const lbem_s* h) { return h->keep != nullptr || h->ade != nullptr || ext_of(h).walls(); }
+static size_t medium_size(const lbem_s* h) { return h->prec == LBEM_F64 ? 8 : 4; }
+static size_t pol_bytes(const lbem_s* h) { return h->ade ? (size_t)2 * h->P * h->n * medium_size(h) : 0; }
 
 template <int D, typename TM>
 static hipError_t launch_medium(lbem_s* h, const double* deps, const double* dmu, int* dflag)
 {
     hipLaunchKernelGGL((k_medium<TM>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, deps, dmu, D,
                        h->cfg.w0_vac, geo1(h), (TM*)h->cl2, h->cfg.mu_varies ? h->mu_r : nullptr,
-                       (TM*)h->dlnmu, dflag, bound_of(h));
+                       (TM*)h->dlnmu, dflag, ext_of(h));
     return hipGetLastError();
 }
 
@@ -288,7 +295,7 @@ struct PlainImpl : Impl {
         const double om = 1.0 / h->cfg.tau;
         hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
-                           (int)(h->cfg.tau == 0.5), bound_of(h));
+                           (int)(h->cfg.tau == 0.5), ext_of(h));
         return hipGetLastError();
     }
     template <int RM, int WM>
@@ -343,7 +350,7 @@ struct PlainImpl : Impl {
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         const T* a = (const T*)h->pop[h->cur];
-        const Bound bc = bound_of(h);
+        const CellExt bc = ext_of(h);
         if (h->layout == LAYOUT_NATURAL)
             return launch_fields<D, T>(h, PlainReader<D, T, R_LOCAL>{a, h->n, bc}, E, B, partials);
         if (h->layout == LAYOUT_PULL_PENDING)
@@ -396,7 +403,7 @@ struct DevImpl : Impl {
         hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
-                           (int)(h->cfg.tau == 0.5), bound_of(h));
+                           (int)(h->cfg.tau == 0.5), ext_of(h));
         return hipGetLastError();
     }
     template <int RM>
@@ -427,10 +434,10 @@ struct DevImpl : Impl {
     {
         if (h->layout == LAYOUT_NATURAL)
             return launch_fields<D, float>(h, DevReader<D, H, GH, R_LOCAL>{M(h, h->cur), Dv(h, h->cur), h->n,
-                                                                            bound_of(h)},
+                                                                            ext_of(h)},
                                            E, B, partials);
         return launch_fields<D, float>(h, DevReader<D, H, GH, R_PULL>{M(h, h->cur), Dv(h, h->cur), h->n,
-                                                                       bound_of(h)}, E,
+                                                                       ext_of(h)}, E,
                                        B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
@@ -824,6 +831,8 @@ int lbem_destroy(lbem_t h)
     (void)hipStreamSynchronize(h->stream);
     free_source(h);
     if (h->keep) (void)hipFree(h->keep);
+    if (h->ade) (void)hipFree(h->ade);
+    if (h->pol) (void)hipFree(h->pol);
     if (h->partials) (void)hipFree(h->partials);
     if (h->own_mem && h->arena) (void)hipFree(h->arena);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
@@ -885,6 +894,7 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B)
     hipError_t e = hipMemcpyAsync(dE, E, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dB, B, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = h->impl->init(h, dE, dB);
+    if (e == hipSuccess && h->pol) e = hipMemsetAsync(h->pol, 0, pol_bytes(h), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(dE);
     (void)hipFree(dB);
@@ -900,6 +910,50 @@ int lbem_set_boundary(lbem_t h, int axis, int kind)
     if (kind != LBEM_BC_PERIODIC && h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
     if (h->have_medium) return LBEM_ESTATE;
     h->bc_kind[axis] = kind;
+    return LBEM_OK;
+}
+
+int lbem_set_dispersion(lbem_t h, const double* wp2, const double* w02, const double* gamma)
+{
+    if (!h) return LBEM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
+    if (!wp2) {
+        if (h->ade) (void)hipFree(h->ade);
+        if (h->pol) (void)hipFree(h->pol);
+        h->ade = h->pol = nullptr;
+        return LBEM_OK;
+    }
+    if (h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+    const int64_t n = h->n;
+    for (int64_t c = 0; c < n; ++c) {
+        const double a = wp2[c], b = w02 ? w02[c] : 0.0, g = gamma ? gamma[c] : 0.0;
+        if (!(a >= 0.0) || !(b >= 0.0) || !(g >= 0.0) || !std::isfinite(a) || !std::isfinite(b) ||
+            !std::isfinite(g))
+            return LBEM_EINVAL;
+    }
+    const bool f64 = h->prec == LBEM_F64;
+    const size_t tm = f64 ? 8 : 4;
+    std::vector<char> host((size_t)3 * n * tm);
+    for (int64_t c = 0; c < n; ++c) {
+        const double g = gamma ? gamma[c] : 0.0, den = 1.0 + 0.5 * g;
+        const double co[3] = {(1.0 - 0.5 * g) / den, wp2[c] / den, (w02 ? w02[c] : 0.0) / den};
+        for (int k = 0; k < 3; ++k) {
+            if (f64) ((double*)host.data())[k * n + c] = co[k];
+            else ((float*)host.data())[k * n + c] = (float)co[k];
+        }
+    }
+    const size_t pb = (size_t)2 * h->P * n * tm;
+    if (!h->ade) {
+        if (hipMalloc(&h->ade, (size_t)3 * n * tm) != hipSuccess) { h->ade = nullptr; return LBEM_ENOMEM; }
+        if (hipMalloc(&h->pol, pb) != hipSuccess) {
+            (void)hipFree(h->ade);
+            h->ade = h->pol = nullptr;
+            return LBEM_ENOMEM;
+        }
+    }
+    if (hipMemcpyAsync(h->ade, host.data(), (size_t)3 * n * tm, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->pol, 0, pb, h->stream) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+        return LBEM_EDEVICE;
     return LBEM_OK;
 }
 
@@ -1116,6 +1170,7 @@ struct StateHeader {
     int32_t dim, prec, streaming, layout;
     int64_t nx, ny, nz, t;
     uint64_t payload;
+    uint64_t aux;      // auxiliary dispersion fields after the populations (0 if none)
 };
 static_assert(sizeof(StateHeader) <= STATE_HDR, "state header");
 const char STATE_MAGIC[8] = {'L', 'B', 'E', 'M', 'S', 'T', '0', '1'};
@@ -1124,7 +1179,7 @@ const char STATE_MAGIC[8] = {'L', 'B', 'E', 'M', 'S', 'T', '0', '1'};
 size_t lbem_state_bytes(lbem_t h)
 {
     if (!h) return 0;
-    return STATE_HDR + sizes_of(&h->cfg).pop_one;
+    return STATE_HDR + sizes_of(&h->cfg).pop_one + pol_bytes(h);
 }
 
 int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device)
@@ -1143,6 +1198,7 @@ int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device)
     sh.nz = h->cfg.nz;
     sh.t = h->t;
     sh.payload = sizes_of(&h->cfg).pop_one;
+    sh.aux = pol_bytes(h);
     std::memcpy(hdr, &sh, sizeof(sh));
     char* out = (char*)buf;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1153,6 +1209,7 @@ int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device)
         std::memcpy(out, hdr, STATE_HDR);
     }
     HIP_OK(hipMemcpyAsync(out + STATE_HDR, h->pop[h->cur], sh.payload, k, h->stream));
+    if (sh.aux) HIP_OK(hipMemcpyAsync(out + STATE_HDR + sh.payload, h->pol, sh.aux, k, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     return LBEM_OK;
 }
@@ -1172,7 +1229,8 @@ int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
     const size_t pay = sizes_of(&h->cfg).pop_one;
     if (std::memcmp(sh.magic, STATE_MAGIC, 8) != 0 || sh.dim != h->D || sh.prec != h->prec ||
         sh.streaming != h->streaming || sh.nx != h->cfg.nx || sh.ny != h->cfg.ny || sh.nz != h->cfg.nz ||
-        sh.payload != pay || sh.t < 0 || sh.layout < LAYOUT_NATURAL || sh.layout > LAYOUT_AA_SWAPPED)
+        sh.payload != pay || sh.aux != pol_bytes(h) || sh.t < 0 || sh.layout < LAYOUT_NATURAL ||
+        sh.layout > LAYOUT_AA_SWAPPED)
         return LBEM_EINVAL;
     // pull steps never leave the AA layout, AA steps never the pull one
     if ((h->streaming == LBEM_STREAM_PULL && sh.layout == LAYOUT_AA_SWAPPED) ||
@@ -1180,6 +1238,7 @@ int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
         return LBEM_EINVAL;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIP_OK(hipMemcpyAsync(h->pop[0], in + STATE_HDR, pay, k, h->stream));
+    if (sh.aux) HIP_OK(hipMemcpyAsync(h->pol, in + STATE_HDR + pay, sh.aux, k, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     h->cur = 0;
     h->layout = sh.layout;
