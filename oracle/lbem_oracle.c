@@ -49,6 +49,21 @@
  *    multiplied by 1 - sigma(x); E and B decay at the same rate, so the
  *    layer's electric and magnetic losses stay in the ratio eps : mu (an
  *    impedance-matched absorber).
+ *  - Anisotropic media (the lattice section notes that different weights
+ *    for particles moving along different axes model them): per-axis
+ *    moving weights w_a, per-axis second moments s_a = 2 w_a, rest weight
+ *    w0 = 1 - sum_a s_a, and c^2 in the equilibrium their mean (1/D) sum_a
+ *    s_a.  The equilibrium keeps its form (w_i/c^2)[Lambda + c_ia Bbar_b -
+ *    c_ib Bbar_a] with these weights; Bbar generalises K/(D-1) so that the
+ *    equilibrium carries the cell's K: Bbar_b = K_b / sum_{a != b} r_a with
+ *    r_a = 2 w_a / c^2 (all r_a = 1 when isotropic).  The equilibrium is
+ *    then the orthogonal projection onto the conserved moments in the 1/w_i
+ *    inner product, so at tau = 1/2 the collision is an isometry and Q_c is
+ *    conserved wherever the ratios r_a are uniform.  A wave along axis a
+ *    polarised along b travels at c^2 = s_a^2/(s_a + s_b) in 3D and at s_a
+ *    in 2D (isotropic: s/(D-1)).  Per cell the user gives factors f_a > 0 on
+ *    the isotropic c_L^2: s_a = f_a c_L^2; eps_abs becomes (D-1)/(mu c^2).
+ *    Equal factors give the isotropic scheme.
  *  - Frequency-dispersive permittivity (the convolution term of the source,
  *    which the paper defers to auxiliary differential equations): one
  *    Lorentz pole per cell, chi(w) = wp2 / (w02 - w^2 - i gamma w), relative
@@ -94,6 +109,7 @@ typedef struct {
     double *g, *gs;       /* [n][Q][D][D] populations, streamed copy */
     double *jd;           /* [3][n] current-density footprint (weights) */
     double *keep;         /* [n] 1 - sigma of the absorbing layer, or NULL */
+    double *wax;          /* [3][n] per-axis moving weights (anisotropic), or NULL */
     double *ade;          /* [3][n] wp2, w02, gamma of the Lorentz pole, or NULL */
     double *pol, *pcur;   /* [3][n] P and J (per field component) */
     int bc[3];            /* per axis: 0 periodic, 1 PEC wall, 2 PMC wall */
@@ -129,6 +145,12 @@ static double weight(int i, double w0, int D)
     return i == 0 ? w0 : (1.0 - w0) / (2.0 * D);
 }
 
+/* isotropic weights of all velocities from the rest weight */
+static void iso_weights(int D, double w0, double* w)
+{
+    for (int i = 0; i < 2 * D + 1; ++i) w[i] = weight(i, w0, D);
+}
+
 static long wrap(long v, long n) { v %= n; return v < 0 ? v + n : v; }
 
 static long neighbour(const orc_t* o, long x, const int* d, int sign)
@@ -154,18 +176,40 @@ static long medium_neighbour(const orc_t* o, long x, int k, int sign)
 
 #define GI(o, x, i, a, b) ((((size_t)(x) * (o)->Q + (i)) * (o)->D + (a)) * (o)->D + (b))
 
+/* Bbar from K: Bbar_b = K_b / sum_{a != b} 2 w_a / c^2 (K/(D-1) when isotropic);
+ * w holds the weights of all velocities, velocity 1+a moving along +a. */
+static void bbar_of(int D, const double* w, double cl2, const double* K, double* Bbar)
+{
+    for (int b = 0; b < D; ++b) {
+        double rs = 0.0;
+        for (int a = 0; a < D; ++a)
+            if (a != b) rs += 2.0 * w[1 + a] / cl2;
+        Bbar[b] = K[b] / rs;
+    }
+}
+
+/* weights of all velocities at cell x (per-axis when the medium is anisotropic) */
+static void cell_weights(const orc_t* o, long x, double* w)
+{
+    iso_weights(o->D, o->w0[x], w);
+    if (o->wax)
+        for (int i = 1; i < o->Q; ++i)
+            for (int a = 0; a < o->D; ++a)
+                if (o->c[i][a] != 0) w[i] = o->wax[a * o->n + x];
+}
+
 /* ------------------------------------------------------------------------
  * Equilibrium of eq. distrib.func:
  *   g0_{i,a,b} = (w_i/c^2) [ Lambda_{a,b} + c_{i,a} Bbar_b - c_{i,b} Bbar_a ]
  * The wedge term is evaluated as one difference so that the result is
  * exactly antisymmetric in (a,b) under IEEE arithmetic.
  * ------------------------------------------------------------------------ */
-static void equilibrium(int D, const int c[7][3], double w0, double cl2,
+static void equilibrium(int D, const int c[7][3], const double* w, double cl2,
                         const double* Lam, const double* Bbar, double* out)
 {
     int Q = 2 * D + 1;
     for (int i = 0; i < Q; ++i) {
-        double wc = weight(i, w0, D) / cl2;
+        double wc = w[i] / cl2;
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b) {
                 double wedge = c[i][a] * Bbar[b] - c[i][b] * Bbar[a];
@@ -206,18 +250,18 @@ static void efield(int D, const double* Lam, double* E)
 
 /* One cell's collision (eq. COLLI) with tensor source
  * T_{i,a,b} = -(w_i/c^2) eps_{gamma a b} S_gamma. */
-static void collide_cell(int D, const int c[7][3], double w0, double cl2, double tau,
+static void collide_cell(int D, const int c[7][3], const double* w, double cl2, double tau,
                          const double* gc, const double* S, double* out)
 {
     int Q = 2 * D + 1;
     double rho[9], K[3], Lam[9], Bbar[3], geq[63];
     moments(D, c, gc, rho, K);
     for (int k = 0; k < D * D; ++k) Lam[k] = cl2 * rho[k];
-    for (int b = 0; b < D; ++b) Bbar[b] = K[b] / (double)(D - 1);
-    equilibrium(D, c, w0, cl2, Lam, Bbar, geq);
+    bbar_of(D, w, cl2, K, Bbar);
+    equilibrium(D, c, w, cl2, Lam, Bbar, geq);
     double om = 1.0 / tau;
     for (int i = 0; i < Q; ++i) {
-        double wc = weight(i, w0, D) / cl2;
+        double wc = w[i] / cl2;
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b) {
                 double es = 0.0;
@@ -264,6 +308,7 @@ void orc_destroy(orc_t* o)
 {
     if (o) {
         free(o->keep);
+        free(o->wax);
         free(o->ade);
         free(o->pol);
         free(o->pcur);
@@ -290,6 +335,8 @@ int orc_set_medium(orc_t* o, const double* eps_r, const double* mu_r)
     int D = o->D;
     double cvac2 = (1.0 - o->w0_vac) / (double)(D * (D - 1));
     o->has_mu = 0;
+    free(o->wax);
+    o->wax = NULL;
     for (long x = 0; x < o->n; ++x) {
         double e = eps_r[x], m = mu_r ? mu_r[x] : 1.0;
         if (!(e > 0.0) || !(m > 0.0) || !isfinite(e) || !isfinite(m)) return ORC_EINVAL;
@@ -326,8 +373,10 @@ int orc_init_fields(orc_t* o, const double* E, const double* B)
                 for (int gm = 0; gm < 3; ++gm) s += levi(gm, a, b) * E[gm * n + x];
                 Lam[a * D + b] = -s;
             }
-        for (int b = 0; b < D; ++b) Bbar[b] = B[b * n + x] / (double)(D - 1);
-        equilibrium(D, o->c, o->w0[x], o->cL2[x], Lam, Bbar, &o->g[GI(o, x, 0, 0, 0)]);
+        double w[7], Bp[3] = {B[x], B[n + x], B[2 * n + x]};
+        cell_weights(o, x, w);
+        bbar_of(D, w, o->cL2[x], Bp, Bbar);
+        equilibrium(D, o->c, w, o->cL2[x], Lam, Bbar, &o->g[GI(o, x, 0, 0, 0)]);
     }
     o->t = 0;
     o->have_fields = 1;
@@ -392,7 +441,9 @@ int orc_step(orc_t* o, long nsteps, const double* amp)
                     o->pol[gm * n + x] = Po + Jn;
                 }
             }
-            collide_cell(D, o->c, o->w0[x], o->cL2[x], o->tau, &o->g[GI(o, x, 0, 0, 0)], S, out);
+            double wv[7];
+            cell_weights(o, x, wv);
+            collide_cell(D, o->c, wv, o->cL2[x], o->tau, &o->g[GI(o, x, 0, 0, 0)], S, out);
             if (o->ade)   /* polarisation source: rest particle only */
                 for (int a2 = 0; a2 < D; ++a2)
                     for (int b2 = 0; b2 < D; ++b2) {
@@ -483,6 +534,39 @@ int orc_polarisation(const orc_t* o, double* P, double* J)
     return ORC_OK;
 }
 
+/* Anisotropy factors a[axis][x] > 0 on the isotropic c_L^2 of the medium just
+ * set (set_medium again restores isotropy). */
+int orc_set_anisotropy(orc_t* o, const double* fac)
+{
+    if (!o->have_medium) return ORC_ESTATE;
+    int D = o->D;
+    long n = o->n;
+    for (long x = 0; x < n * D; ++x)
+        if (!(fac[x] > 0.0) || !isfinite(fac[x])) return ORC_EINVAL;
+    double* wax = (double*)calloc(3 * (size_t)n, sizeof(double));
+    if (!wax) return ORC_ENOMEM;
+    for (long x = 0; x < n; ++x) {
+        double sum = 0.0;
+        for (int a = 0; a < D; ++a) sum += fac[a * n + x] * o->cL2[x];
+        double w0 = 1.0 - sum;
+        if (!(w0 >= 0.0 && w0 < 1.0)) { free(wax); return ORC_EUNSTABLE; }
+    }
+    for (long x = 0; x < n; ++x) {
+        double sum = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double sa = fac[a * n + x] * o->cL2[x];
+            wax[a * n + x] = 0.5 * sa;
+            sum += sa;
+        }
+        o->w0[x] = 1.0 - sum;
+        o->cL2[x] = sum / (double)D;
+        o->eps_abs[x] = (double)(D - 1) / (o->mu_r[x] * o->cL2[x]);
+    }
+    free(o->wax);
+    o->wax = wax;
+    return ORC_OK;
+}
+
 /* Absorbing layer: per-cell sigma in [0,1) (NULL removes it). */
 int orc_set_absorber(orc_t* o, const double* sigma)
 {
@@ -534,9 +618,10 @@ int orc_diag(const orc_t* o, double* out)
         double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
         en += o->eps_abs[x] * e2 + b2 / o->mu_r[x];
         bb += b2;
-        double q = 0.0;
+        double q = 0.0, wv[7];
+        cell_weights(o, x, wv);
         for (int i = 0; i < Q; ++i) {
-            double w = weight(i, o->w0[x], D);
+            double w = wv[i];
             if (w == 0.0) continue;
             double s = 0.0;
             for (int a = 0; a < D; ++a)
@@ -594,7 +679,9 @@ int orc_equilibrium(int D, double w0, const double* Lam, const double* Bbar, dou
     int c[7][3];
     if (D != 2 && D != 3) return ORC_EINVAL;
     velocities(D, c);
-    equilibrium(D, c, w0, (1.0 - w0) / D, Lam, Bbar, out);
+    double w[7];
+    iso_weights(D, w0, w);
+    equilibrium(D, c, w, (1.0 - w0) / D, Lam, Bbar, out);
     return ORC_OK;
 }
 
@@ -603,7 +690,9 @@ int orc_collide(int D, double w0, double tau, const double* g, const double* S, 
     int c[7][3];
     if (D != 2 && D != 3) return ORC_EINVAL;
     velocities(D, c);
-    collide_cell(D, c, w0, (1.0 - w0) / D, tau, g, S, out);
+    double w[7];
+    iso_weights(D, w0, w);
+    collide_cell(D, c, w, (1.0 - w0) / D, tau, g, S, out);
     return ORC_OK;
 }
 

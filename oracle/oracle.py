@@ -53,6 +53,7 @@ def lib():
         L.orc_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_set_absorber.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_set_dispersion.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_anisotropy.argtypes = [C.c_void_p, dp]
         L.orc_polarisation.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
@@ -138,6 +139,13 @@ class Oracle:
         else:
             s = np.ascontiguousarray(sigma, np.float64).ravel()
             _chk(lib().orc_set_absorber(self._h, s.ctypes.data_as(C.c_void_p)))
+
+    def set_anisotropy(self, factors):
+        """Per-axis factors a[axis][cell] > 0 on the isotropic c_L^2 of the
+        medium (after set_medium; set_medium again restores isotropy)."""
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(factors, np.float64).reshape(self.dim, -1),
+                                                 (self.dim, self.n)))
+        _chk(lib().orc_set_anisotropy(self._h, f.reshape(-1)))
 
     def set_dispersion(self, wp2=None, w02=None, gamma=None):
         """One Lorentz pole per cell, chi(w) = wp2/(w02 - w^2 - i gamma w)
