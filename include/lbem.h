@@ -205,6 +205,23 @@ int lbem_set_boundary(lbem_t h, int axis, int kind);
  * streaming only.  The handle copies sigma; synchronises. */
 int lbem_set_absorber(lbem_t h, const double* sigma);
 
+/* ---- anisotropic media ----
+ * The lattice section notes that different weights for particles moving
+ * along different axes model anisotropic media.  Factors fac[a*n + x] > 0
+ * (a = 0..dim-1) scale the isotropic c_L^2(x) of the medium along axis a:
+ * per-axis second moments s_a = fac_a c_L^2, rest weight 1 - sum_a s_a (in
+ * [0,1), else EUNSTABLE and nothing changes), c^2 = mean_a s_a.  The
+ * equilibrium keeps the paper's form with these weights and
+ * Bbar_b = K_b / sum_{a != b} r_a (r_a = s_a/c^2; K/(D-1) when isotropic):
+ * the orthogonal projection onto the conserved moments, so the collision
+ * stays an isometry.  A wave along axis a travels at s_a (2D) and at
+ * s_a^2/(s_a + s_b) polarised along b (3D); the medium is birefringent in 3D.
+ * eps_abs becomes (D-1)/(mu c^2).  Plain formats (F64, F32) with pull
+ * streaming only (EINVAL otherwise); after lbem_set_medium (ESTATE before;
+ * lbem_set_medium again makes the medium isotropic).  The fields must be
+ * initialised afterwards.  Synchronises; the solver then runs single steps. */
+int lbem_set_anisotropy(lbem_t h, const double* fac);
+
 /* ---- frequency-dispersive permittivity ----
  * The convolution term of the Maxwell source (Section "The Maxwell
  * Equations"), which the paper leaves to auxiliary differential equations:

@@ -110,6 +110,7 @@ struct CellExt {
     const void* keep;      // per-cell 1 - sigma (medium precision), or nullptr
     const void* ade;       // [3][n] c1, c2, c3 (medium precision), or nullptr
     void* pol;             // [2P][n] P_p then J_p, updated in place by the cell's thread
+    const void* ra;        // [D][n] anisotropy ratios r_a = s_a / c^2 (plain formats), or nullptr
     __host__ __device__ bool walls() const { return (kind[0] | kind[1] | kind[2]) != 0; }
 };
 
@@ -284,6 +285,47 @@ __device__ __forceinline__ void collide(const T (&f)[Lat<D>::Q][Lat<D>::P], T cl
     }
 }
 
+// Anisotropic collision: per-axis weights w_a = r_a c^2 / 2 (r_a = s_a/c^2,
+// s_a the per-axis second moment, c^2 their mean).  The equilibrium keeps the
+// form (w_i/c^2)[Lambda + c_ia Bbar_b - c_ib Bbar_a] with Bbar_b = K_b /
+// sum_{a != b} r_a, the orthogonal projection onto the conserved moments in
+// the 1/w_i inner product (all r_a = 1 is the isotropic collide()).
+template <int D, typename T>
+__device__ __forceinline__ void collide_an(const T (&f)[Lat<D>::Q][Lat<D>::P], T cl2, const T (&r)[D],
+                                           const T (&Sp)[Lat<D>::P], bool any_src, T omega, bool tau_half,
+                                           const T (&rho)[Lat<D>::P], const T (&K)[D],
+                                           T (&out)[Lat<D>::Q][Lat<D>::P])
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    T Lam[P], Bb[D];
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lam[p] = cl2 * rho[p];
+    T rsum = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) rsum += r[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bb[b] = K[b] / (rsum - r[b]);
+    const T wc0 = any_src ? (T(1) / cl2 - rsum) : T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const T geq = rho[p] - rsum * Lam[p];       // w0 rho as the remainder (see collide())
+        T o = tau_half ? (geq + geq) - f[0][p] : f[0][p] + omega * (geq - f[0][p]);
+        if (any_src) o -= wc0 * Sp[p];
+        out[0][p] = o;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const T ri = r[vaxis(D, i)];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const T A = ri * twice_eq_moving<D, T>(i, p, Lam[p], Bb);
+            T o = tau_half ? A - f[i][p] : f[i][p] + omega * (T(0.5) * A - f[i][p]);
+            if (any_src) o -= T(0.5) * ri * Sp[p];
+            out[i][p] = o;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // block decomposition shared by the step kernels
 // ---------------------------------------------------------------------------
@@ -380,7 +422,14 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
         const bool ade = BX && bc.ade != nullptr;
         if (ade) ade_update<D, T>(bc, g.n, C.c, cl2, rho, Jn);
         T out[Q][P];
-        collide<D, T>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        if (BX && bc.ra) {
+            T r[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = ((const T*)bc.ra)[(int64_t)a * g.n + C.c];
+            collide_an<D, T>(f, cl2, r, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        } else {
+            collide<D, T>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+        }
         if (ade) {
 #pragma unroll
             for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
@@ -1276,7 +1325,8 @@ struct Geo1 {
 template <int D, typename TM, class R>
 __global__ __launch_bounds__(NT) void k_fields(const R rd, const TM* __restrict__ cl2a,
                                                const double* __restrict__ mu_r, const Geo1 g1,
-                                               double* E, double* B, double* partials)
+                                               double* E, double* B, double* partials,
+                                               const TM* __restrict__ ra)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     __shared__ double sh[4];
@@ -1316,15 +1366,24 @@ __global__ __launch_bounds__(NT) void k_fields(const R rd, const TM* __restrict_
             const double e2 = Ev[0] * Ev[0] + Ev[1] * Ev[1] + Ev[2] * Ev[2];
             b2 = Bv[0] * Bv[0] + Bv[1] * Bv[1] + Bv[2] * Bv[2];
             en = eps_abs * e2 + b2 / mu;
-            const double w0 = 1.0 - (double)D * cl2;
+            double rr[D], rs = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                rr[a] = ra ? (double)ra[(int64_t)a * g1.n + c] : 1.0;
+                rs += rr[a];
+            }
+            const double w0 = 1.0 - rs * cl2;
             double sm = 0.0, s0 = 0.0;
 #pragma unroll
             for (int p = 0; p < P; ++p) s0 += f[0][p] * f[0][p];
 #pragma unroll
-            for (int i = 1; i < Q; ++i)
+            for (int i = 1; i < Q; ++i) {
+                double si = 0.0;
 #pragma unroll
-                for (int p = 0; p < P; ++p) sm += f[i][p] * f[i][p];
-            // c_L^2 / w_i = 2 for moving particles; rest skipped when w0 = 0
+                for (int p = 0; p < P; ++p) si += f[i][p] * f[i][p];
+                sm += ra ? si / rr[vaxis(D, i)] : si;
+            }
+            // c_L^2 / w_i = 2 / r_a for moving particles; rest skipped when w0 = 0
             qc = 2.0 * sm + (w0 > 0.0 ? cl2 / w0 * s0 : 0.0);
         }
     }
@@ -1422,33 +1481,73 @@ __global__ __launch_bounds__(NT) void k_medium(const double* __restrict__ eps, c
 template <int D>
 __device__ __forceinline__ void init_eq(const double* E, const double* B, int64_t n, int c, double cl2,
                                         double (&g0)[Lat<D>::Q][Lat<D>::P], double (&Lam)[Lat<D>::P],
-                                        double (&Bb)[D])
+                                        double (&Bb)[D], const double (&r)[D])
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    double rs = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) rs += r[a];
 #pragma unroll
     for (int p = 0; p < P; ++p) Lam[p] = -(double)pair_s(D, p) * E[(int64_t)pair_g(D, p) * n + c];
 #pragma unroll
-    for (int b = 0; b < D; ++b) Bb[b] = B[(int64_t)b * n + c] / (double)(D - 1);
-    const double w0 = 1.0 - (double)D * cl2;
+    for (int b = 0; b < D; ++b) Bb[b] = B[(int64_t)b * n + c] / (rs - r[b]);
+    const double w0 = 1.0 - rs * cl2;
     const double wc = w0 / cl2;
 #pragma unroll
     for (int p = 0; p < P; ++p) g0[0][p] = wc * Lam[p];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
 #pragma unroll
-        for (int p = 0; p < P; ++p) g0[i][p] = 0.5 * twice_eq_moving<D, double>(i, p, Lam[p], Bb);
+        for (int p = 0; p < P; ++p) g0[i][p] = 0.5 * r[vaxis(D, i)] * twice_eq_moving<D, double>(i, p, Lam[p], Bb);
+}
+
+// per-axis ratios of one cell (1 when isotropic)
+template <int D, typename TM>
+__device__ __forceinline__ void ratios(const TM* ra, int64_t n, int c, double (&r)[D])
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] = ra ? (double)ra[(int64_t)a * n + c] : 1.0;
+}
+
+// Anisotropy: factors f_a on the isotropic c_L^2 give the per-axis second
+// moments s_a = f_a c_L^2; c_L^2 becomes their mean and ra the ratios
+// s_a / c^2.  flag is set where the rest weight 1 - sum s_a leaves [0,1).
+template <typename TM>
+__global__ __launch_bounds__(NT) void k_aniso(const double* __restrict__ fac, int D, int64_t n, TM* cl2, TM* ra,
+                                              int* flag, int write)
+{
+    const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (c >= n) return;
+    const double cb = (double)cl2[c];
+    double s[3], sum = 0.0;
+    bool bad = false;
+    for (int a = 0; a < D; ++a) {
+        const double f = fac[a * n + c];
+        bad = bad || !(f > 0.0) || !isfinite(f);
+        s[a] = f * cb;
+        sum += s[a];
+    }
+    const double w0 = 1.0 - sum;
+    bad = bad || !(w0 >= 0.0 && w0 < 1.0);
+    if (bad) atomicOr(flag, 1);
+    if (bad || !write) return;   // the first pass only validates, so a rejected call changes nothing
+    const double cbar = sum / (double)D;
+    for (int a = 0; a < D; ++a) ra[a * n + c] = (TM)(s[a] / cbar);
+    cl2[c] = (TM)cbar;
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E, const double* __restrict__ B,
-                                                   const T* __restrict__ cl2a, int64_t n, T* pop)
+                                                   const T* __restrict__ cl2a, int64_t n, T* pop,
+                                                   const T* __restrict__ ra)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     const int64_t c64 = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (c64 >= n) return;
     const int c = (int)c64;
-    double g0[Q][P], Lam[P], Bb[D];
-    init_eq<D>(E, B, n, c, (double)cl2a[c], g0, Lam, Bb);
+    double g0[Q][P], Lam[P], Bb[D], r[D];
+    ratios<D, T>(ra, n, c, r);
+    init_eq<D>(E, B, n, c, (double)cl2a[c], g0, Lam, Bb, r);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
@@ -1465,7 +1564,10 @@ __global__ __launch_bounds__(NT) void k_init_dev(const double* __restrict__ E, c
     const int c = (int)c64;
     const float cl2 = cl2a[c];
     double g0[Q][P], Lam[P], Bb[D];
-    init_eq<D>(E, B, n, c, (double)cl2, g0, Lam, Bb);
+    double r1[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) r1[a] = 1.0;   // the 16-bit formats are isotropic
+    init_eq<D>(E, B, n, c, (double)cl2, g0, Lam, Bb, r1);
     float Lf[P], Bf[D];
 #pragma unroll
     for (int p = 0; p < P; ++p) Lf[p] = (float)Lam[p];

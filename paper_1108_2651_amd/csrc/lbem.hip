@@ -144,6 +144,9 @@ struct lbem_s {
     // frequency-dispersive permittivity (one Lorentz pole per cell)
     void* ade;               // [3][n] coefficients, handle-owned, or nullptr
     void* pol;               // [2P][n] auxiliary P and J per pair
+    // anisotropy (plain formats): [D][n] ratios r_a, handle-owned; valid while ra_set
+    void* ra;
+    bool ra_set;
     int64_t t;
     bool have_medium, have_fields;
     Impl* impl;
@@ -185,10 +188,14 @@ static CellExt ext_of(const lbem_s* h)
     b.keep = h->keep;
     b.ade = h->ade;
     b.pol = h->pol;
+    b.ra = h->ra_set ? h->ra : nullptr;
     return b;
 }
 // walls, an absorber or dispersion: the single-step kernels with cell extras
-static bool has_bx(const lbem_s* h) { return h->keep != nullptr || h->ade != nullptr || ext_of(h).walls(); }
+static bool has_bx(const lbem_s* h)
+{
+    return h->keep != nullptr || h->ade != nullptr || h->ra_set || ext_of(h).walls();
+}
 static size_t medium_size(const lbem_s* h) { return h->prec == LBEM_F64 ? 8 : 4; }
 static size_t pol_bytes(const lbem_s* h) { return h->ade ? (size_t)2 * h->P * h->n * medium_size(h) : 0; }
 
@@ -201,11 +208,20 @@ static hipError_t launch_medium(lbem_s* h, const double* deps, const double* dmu
     return hipGetLastError();
 }
 
+template <typename TM>
+static hipError_t launch_aniso(lbem_s* h, const double* dfac, int* dflag, int write)
+{
+    hipLaunchKernelGGL((k_aniso<TM>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dfac, h->D, h->n,
+                       (TM*)h->cl2, (TM*)h->ra, dflag, write);
+    return hipGetLastError();
+}
+
 template <int D, typename TM, class R>
 static hipError_t launch_fields(lbem_s* h, const R& rd, double* E, double* B, double* partials)
 {
     hipLaunchKernelGGL((k_fields<D, TM, R>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, rd,
-                       (const TM*)h->cl2, h->mu_set ? h->mu_r : nullptr, geo1(h), E, B, partials);
+                       (const TM*)h->cl2, h->mu_set ? h->mu_r : nullptr, geo1(h), E, B, partials,
+                       (const TM*)(h->ra_set ? h->ra : nullptr));
     return hipGetLastError();
 }
 
@@ -362,7 +378,7 @@ struct PlainImpl : Impl {
         h->cur = 0;
         h->layout = LAYOUT_NATURAL;
         hipLaunchKernelGGL((k_init_plain<D, T>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
-                           (const T*)h->cl2, h->n, (T*)h->pop[0]);
+                           (const T*)h->cl2, h->n, (T*)h->pop[0], (const T*)(h->ra_set ? h->ra : nullptr));
         return hipGetLastError();
     }
     hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) override
@@ -833,6 +849,7 @@ int lbem_destroy(lbem_t h)
     if (h->keep) (void)hipFree(h->keep);
     if (h->ade) (void)hipFree(h->ade);
     if (h->pol) (void)hipFree(h->pol);
+    if (h->ra) (void)hipFree(h->ra);
     if (h->partials) (void)hipFree(h->partials);
     if (h->own_mem && h->arena) (void)hipFree(h->arena);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
@@ -864,6 +881,7 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
     if (e == hipSuccess && mu_r) e = hipMemcpyAsync(dmu, mu_r, n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(dflag, 0, sizeof(int), h->stream);
     h->mu_set = h->cfg.mu_varies != 0;
+    h->ra_set = false;                 // a new medium is isotropic until lbem_set_anisotropy
     if (e == hipSuccess) e = h->impl->medium(h, deps, dmu, dflag);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -911,6 +929,43 @@ int lbem_set_boundary(lbem_t h, int axis, int kind)
     if (h->have_medium) return LBEM_ESTATE;
     h->bc_kind[axis] = kind;
     return LBEM_OK;
+}
+
+int lbem_set_anisotropy(lbem_t h, const double* fac)
+{
+    if (!h || !fac) return LBEM_EINVAL;
+    if (h->prec > LBEM_F32 || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+    if (!h->have_medium) return LBEM_ESTATE;
+    const int64_t n = h->n;
+    const size_t tm = h->prec == LBEM_F64 ? 8 : 4;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
+    if (!h->ra && hipMalloc(&h->ra, (size_t)h->D * n * tm) != hipSuccess) {
+        h->ra = nullptr;
+        return LBEM_ENOMEM;
+    }
+    double* dfac = nullptr;
+    int* dflag = nullptr;
+    if (hipMalloc((void**)&dfac, (size_t)h->D * n * 8) != hipSuccess) return LBEM_ENOMEM;
+    if (hipMalloc((void**)&dflag, sizeof(int)) != hipSuccess) { (void)hipFree(dfac); return LBEM_ENOMEM; }
+    int flag = 0, rc = LBEM_OK;
+    hipError_t e = hipMemcpyAsync(dfac, fac, (size_t)h->D * n * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(dflag, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = tm == 8 ? launch_aniso<double>(h, dfac, dflag, 0) : launch_aniso<float>(h, dfac, dflag, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && !flag) {
+        e = tm == 8 ? launch_aniso<double>(h, dfac, dflag, 1) : launch_aniso<float>(h, dfac, dflag, 1);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    if (e != hipSuccess) rc = LBEM_EDEVICE;
+    else if (flag) rc = LBEM_EUNSTABLE;
+    (void)hipFree(dfac);
+    (void)hipFree(dflag);
+    if (rc == LBEM_OK) {
+        h->ra_set = true;
+        h->have_fields = false;        // the populations must be re-initialised for the new weights
+    }
+    return rc;
 }
 
 int lbem_set_dispersion(lbem_t h, const double* wp2, const double* w02, const double* gamma)

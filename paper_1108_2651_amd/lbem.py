@@ -25,7 +25,7 @@ SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_mediu
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
            "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
            "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state",
-           "lbem_set_boundary", "lbem_set_absorber", "lbem_set_dispersion")
+           "lbem_set_boundary", "lbem_set_absorber", "lbem_set_dispersion", "lbem_set_anisotropy")
 BOUNDARY = {"periodic": 0, "pec": 1, "pmc": 2}
 
 
@@ -75,6 +75,7 @@ def load():
     L.lbem_set_boundary.argtypes = [vp, C.c_int, C.c_int]
     L.lbem_set_absorber.argtypes = [vp, vp]
     L.lbem_set_dispersion.argtypes = [vp, vp, vp, vp]
+    L.lbem_set_anisotropy.argtypes = [vp, vp]
     L.lbem_strerror.argtypes = [C.c_int]
     L.lbem_strerror.restype = C.c_char_p
     _lib = L
@@ -188,6 +189,13 @@ class Solver:
         """Absorbing layer sigma(x) in [0,1) per cell; None removes it."""
         s = None if sigma is None else _f64(sigma, self.n)
         self._chk(load().lbem_set_absorber(self._h, _ptr(s)), "lbem_set_absorber")
+
+    def set_anisotropy(self, factors):
+        """Per-axis factors [dim][n] (or [dim], broadcast) on the isotropic c_L^2
+        (after set_medium, before init_fields)."""
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(factors, np.float64).reshape(self.dim, -1),
+                                                 (self.dim, self.n)))
+        self._chk(load().lbem_set_anisotropy(self._h, _ptr(f)), "lbem_set_anisotropy")
 
     def set_dispersion(self, wp2=None, w02=None, gamma=None):
         """One Lorentz pole per cell (lattice units); scalars broadcast; wp2=None
