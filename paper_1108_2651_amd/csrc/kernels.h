@@ -606,11 +606,13 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // ---------------------------------------------------------------------------
 // A block owns a TX x TY column tile and a chunk of lz planes.  For every
 // plane zz from z0-1 to z0+lz it runs step 1 on the tile grown by one cell in
-// x and y (pulling the stored state from HBM), keeping in LDS the in-plane
-// components (rest, +-x, +-y: with the halo) and, for tile cells only, the +z
-// components (ring of 3 planes) and -z components (one plane); then it runs
-// step 2 on plane zz-1 of the tile, pulling from LDS, and writes it.  Every
-// update is the same collide() as the single-step kernel: bit-identical.
+// x and y (pulling the stored state from HBM), keeping for tile cells the +z
+// components (LDS ring of 3 planes) and -z components (one plane) and holding
+// the in-plane components (rest, +-x, +-y, halo included) in registers; then
+// it runs step 2 on plane zz-1 of the tile, pulling from LDS, writes it, and
+// only then stores plane zz's in-plane components into the single LDS frame
+// (one frame instead of two keeps three blocks per CU).  Every update is the
+// same collide() as the single-step kernel: bit-identical.
 template <typename T, int TX, int TY, bool MU>
 __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g, const int lz,
@@ -621,7 +623,8 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
     constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;
     static_assert(TC == NT, "one tile cell per thread");
     constexpr int NIP = 5;                       // in-plane velocities 0, +x, +y, -x, -y
-    __shared__ T lin[2][NIP * P][FC];
+    constexpr int CF = (FC + NT - 1) / NT;       // frame cells per thread
+    __shared__ T lin[NIP * P][FC];               // in-plane outputs of plane zz-1 (frame)
     __shared__ T lpz[3][P][TC];
     __shared__ T lmz[P][TC];
     __shared__ T lsrc[2][P][FC];
@@ -658,8 +661,13 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
             }
             __syncthreads();
         }
-        // ---- step 1 on plane zz, frame cells
-        for (int k = threadIdx.x; k < FC; k += NT) {
+        // ---- step 1 on plane zz, frame cells; the in-plane outputs stay in
+        // registers until step 2 has read plane zz-1 from the frame buffer
+        T held[CF][NIP * P];
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            const int k = threadIdx.x + j * NT;
+            if (k >= FC) continue;
             const int hx = k % W, hy = k / W;
             int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
             if (gx < 0) gx += g.nx;
@@ -687,7 +695,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
                 const int sl = ipl(i);
                 if (sl >= 0) {
 #pragma unroll
-                    for (int p = 0; p < P; ++p) lin[bi][sl * P + p][k] = out[i][p];
+                    for (int p = 0; p < P; ++p) held[j][sl * P + p] = out[i][p];
                 }
             }
             const bool tile = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
@@ -706,15 +714,15 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
         if (zc2 >= z0 && zc2 < z1) {
             const int x = x0 + lx, y = y0 + ly;
             if (x < g.nx && y < g.ny) {
-                const int pb = (rel - 1) & 1;       // plane zz-1's in-plane buffer
+                const int pb = (rel - 1) & 1;       // plane zz-1's source buffer
                 T f[Q][P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    f[0][p] = lin[pb][0 * P + p][hc];
-                    f[1][p] = lin[pb][1 * P + p][hc - 1];
-                    f[2][p] = lin[pb][2 * P + p][hc - W];
-                    f[4][p] = lin[pb][3 * P + p][hc + 1];
-                    f[5][p] = lin[pb][4 * P + p][hc + W];
+                    f[0][p] = lin[0 * P + p][hc];
+                    f[1][p] = lin[1 * P + p][hc - 1];
+                    f[2][p] = lin[2 * P + p][hc - W];
+                    f[4][p] = lin[3 * P + p][hc + 1];
+                    f[5][p] = lin[4 * P + p][hc + W];
                     f[3][p] = lpz[(rel + 1) % 3][p][threadIdx.x];   // plane zz-2, moving +z
                     f[6][p] = lmz[p][threadIdx.x];                   // plane zz, moving -z
                 }
@@ -738,6 +746,15 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
             }
         }
         __syncthreads();
+        // ---- plane zz's in-plane outputs into the frame buffer (read by the
+        // next iteration's step 2, after its step-1 barrier)
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            const int k = threadIdx.x + j * NT;
+            if (k >= FC) continue;
+#pragma unroll
+            for (int q = 0; q < NIP * P; ++q) lin[q][k] = held[j][q];
+        }
     }
 }
 
