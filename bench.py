@@ -49,6 +49,22 @@ def bytes_per_cell(dim: int, prec: str, mu: bool = False) -> int:
     return 2 * ((P + dim) * 4 + slots * 2) + 4 + extra
 
 
+def extra_bytes(p, prec: str) -> int:
+    """Algorithmic bytes per cell update of the cell extras: the absorber's
+    1 - sigma, the dispersion pole's 3 coefficients read plus its 2P
+    auxiliary values read and written, the D anisotropy ratios."""
+    tm = 8 if prec == "f64" else 4
+    P = p.dim * (p.dim - 1) // 2
+    extra = 0
+    if getattr(p, "sigma", None) is not None:
+        extra += tm
+    if getattr(p, "disp", None) is not None:
+        extra += 3 * tm + 2 * (2 * P * tm)
+    if getattr(p, "aniso", None) is not None:
+        extra += p.dim * tm
+    return extra
+
+
 def kernel_source_hash() -> str:
     """Hash of the device code and its compiler flags (the launch shape is
     checked separately, by the kernel name recorded with the counters)."""
@@ -91,6 +107,29 @@ def _make_problem(name: str, nsteps: int):
         return I.config4(nsteps=nsteps)
     if name.startswith("3d"):          # "3d128": spheres recipe at another size
         return I.config3(nsteps=nsteps, n=int(name[2:]))
+    if name == "c2walls":              # config2 inside PEC walls with a 32-cell absorbing layer
+        import copy
+        p = copy.copy(_make_problem("c2", nsteps))
+        n = p.shape[0]
+        d = np.minimum(np.arange(n), n - 1 - np.arange(n)).astype(float)
+        prof = np.where(d < 32, 0.05 * ((32 - d - 0.5) / 32) ** 2, 0.0)
+        p.walls = [(0, "pec"), (1, "pec")]
+        p.sigma = np.maximum(prof[None, :], prof[:, None]).ravel()
+        p.name = p.name + "-walls-absorber"
+        return p
+    if name == "c3disp":               # config3 with a Lorentz pole inside the spheres
+        import copy
+        p = copy.copy(_make_problem("c3", nsteps))
+        inside = p.eps_r > 1.0
+        p.disp = (np.where(inside, 0.01, 0.0), np.where(inside, 0.002, 0.0), np.where(inside, 0.001, 0.0))
+        p.name = p.name + "-lorentz"
+        return p
+    if name == "c3aniso":              # config3 with per-axis factors (1.2, 1.0, 0.8)
+        import copy
+        p = copy.copy(_make_problem("c3", nsteps))
+        p.aniso = np.array([1.2, 1.0, 0.8])[:, None] * np.ones((3, p.n))
+        p.name = p.name + "-anisotropic"
+        return p
     if name in ("c2mu", "c3mu"):       # the same media with mu_r = 1 + (eps_r - 1)/3 as well
         import copy
         p = copy.copy(_make_problem(name[:2], nsteps))
@@ -112,7 +151,20 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
         amp = I.ricker(warmup + steps, 1.0 / 80.0)
     s = lbem.Solver(p.dim, p.shape, prec, tau=p.tau, w0_vac=p.w0_vac, streaming=streaming,
                     mu_varies=p.mu_r is not None)
-    s.setup(p)
+    walls, sigma = getattr(p, "walls", None), getattr(p, "sigma", None)
+    disp, aniso = getattr(p, "disp", None), getattr(p, "aniso", None)
+    for a, kind in walls or []:
+        s.set_boundary(a, kind)
+    s.set_medium(p.eps_r, p.mu_r)
+    if aniso is not None:
+        s.set_anisotropy(aniso)
+    if sigma is not None:
+        s.set_absorber(sigma)
+    if disp is not None:
+        s.set_dispersion(*disp)
+    s.init_fields(p.E0, p.B0)
+    if len(p.src_cells):
+        s.set_source(p.src_comp, p.src_cells, p.src_weights)
     spl = s.steps_per_launch
     stream = torch.cuda.current_stream()
     s.step(warmup, amp[:warmup])
@@ -128,7 +180,7 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
     ms = e0.elapsed_time(e1)
     diag = s.energy(check=False)
     n = p.n
-    bpc = bytes_per_cell(p.dim, prec, p.mu_r is not None)
+    bpc = bytes_per_cell(p.dim, prec, p.mu_r is not None) + extra_bytes(p, prec)
     st = streaming if streaming != "auto" else "pull"
     bpu = bpc / max(spl, 1)        # HBM bytes per cell update when spl steps share one pass
     mlups = n * steps / (ms * 1e-3) / 1e6
@@ -305,7 +357,9 @@ def main():
                 ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5),
                 ("c4", "f16ghost", "pull", 50, 5),
                 ("c2mu", "f32", "pull", 1000, 20), ("c3mu", "f32", "auto", 200, 10),
-                ("c3mu", "f16ghost", "pull", 200, 10)]
+                ("c3mu", "f16ghost", "pull", 200, 10), ("c2walls", "f32", "pull", 1000, 20),
+                ("c3disp", "f32", "pull", 200, 10), ("c3disp", "f16ghost", "pull", 200, 10),
+                ("c3aniso", "f32", "pull", 200, 10)]
         plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
         for name, prec, st, k, w in plan:
             print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)

@@ -42,6 +42,26 @@ def sampled_parity(p, prec, k, samples, tol, streaming="auto"):
     assert worst <= tol, worst
 
 
+def test_config2_full_grid_1000_steps_fp32():
+    """The benchmark workload on its whole 2048^2 grid, in the benchmark's
+    launch configuration, against the oracle on the whole grid after 1000
+    steps: relative L2 of E and of B <= 1e-5."""
+    from gpu_util import oracle_run, rel
+    k = 1000
+    p = inputs.config2(nsteps=k)
+    announce("config2 2048^2 fp32 full grid, 1000 steps (oracle on all host cores)")
+    s = lbem.Solver(p.dim, p.shape, "f32", w0_vac=p.w0_vac)
+    s.setup(p)
+    assert s.steps_per_launch == 2
+    s.step(k, p.amp[:k])
+    Eg, Bg = s.moments()
+    s.close()
+    Eo, Bo = oracle_run(p, k).fields()
+    eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+    announce(f"  rel L2 E={eE:.3e} B={eB:.3e}")
+    assert eE <= 1e-5 and eB <= 1e-5, (eE, eB)
+
+
 def test_config2_full_2048_fp32_fused():
     """The benchmark's primary workload and launch configuration (2048^2
     FP32, two time steps per launch), 64 steps, 6 sampled cells including
