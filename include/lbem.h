@@ -132,7 +132,11 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
 
 /* Enqueue nsteps time steps.  amp (host, nsteps doubles, may be NULL = no
  * source) gives the source amplitude of each step: step k of this call uses
- * amp[k] at time t0 + k.  ESTATE before lbem_init_fields. */
+ * amp[k] at time t0 + k.  ESTATE before lbem_init_fields.  Periodic handles in
+ * the plain formats with pull streaming advance several steps per launch
+ * where the kernels allow (lbem_steps_per_launch); walls, an absorber,
+ * dispersion or anisotropy make every launch a single step.  The result does
+ * not depend on this choice (bit for bit). */
 int lbem_step(lbem_t h, int64_t nsteps, const double* amp);
 
 /* E and B at the current time (3*n doubles each, component-major).  With
@@ -143,8 +147,9 @@ int lbem_moments(lbem_t h, double* E, double* B, int on_device);
 /* FP64 diagnostics at the current time (synchronises):
  *   out[0]  EM energy  sum_x eps_abs |E|^2 + |B|^2/mu_r
  *   out[1]  Q_c = sum_x c_L^2 sum_i sum_p g_ip^2 / w_i  (exact invariant of
- *           the scheme at tau = 1/2 with mu == 1 and no source)
- *   out[2]  sum_x (div_h B)^2, central differences
+ *           the scheme at tau = 1/2 with mu == 1, no source, no absorber or
+ *           dispersion, periodic or walled faces, uniform anisotropy ratios)
+ *   out[2]  sum_x (div_h B)^2, periodic central differences (also with walls)
  *   out[3]  sum_x |B|^2
  * ENONFINITE if any of them is NaN or Inf (the values are still written). */
 int lbem_energy(lbem_t h, double out[4]);
@@ -164,7 +169,9 @@ int lbem_steps_per_launch(lbem_t h);
  * handle's population state exactly as stored (format- and streaming-
  * specific; it is not converted).  The medium and the current source are not
  * in the blob: the resuming handle is created with the same configuration and
- * given the same lbem_set_medium / lbem_set_source before lbem_set_state. */
+ * given the same walls, medium, anisotropy, absorber, dispersion parameters
+ * and source (lbem_set_boundary ... lbem_set_source) before lbem_set_state;
+ * the dispersion's auxiliary fields are in the blob. */
 
 /* Size in bytes of the state blob of this handle (0 for NULL). */
 size_t lbem_state_bytes(lbem_t h);
