@@ -274,6 +274,23 @@ def size_sweep(steps: int = 100, warmup: int = 5) -> list:
     return rows
 
 
+SERVING_CONFIG = ("Poisson arrivals; 70% 2D 64^2-1024^2, 30% 3D 32^3-128^3; smooth eps in [1,4]; "
+                  "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 50 steps per tick; "
+                  "latency = arrival to E,B on the host")
+
+
+def serving_run(rate: float, count: int) -> dict:
+    """The continuous-batching serving mix at `rate` requests/s."""
+    from paper_1108_2651_amd import serve as SV
+    reqs = SV.make_requests(count=count, rate=rate)
+    rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=50, workers=6)
+    return dict(requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
+                p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
+                mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,
+                mean_resident=rep.mean_resident, max_resident=rep.max_resident,
+                offered_mlups=sum(r.cells * r.nsteps for r in reqs) / reqs[-1].t_arrive / 1e6)
+
+
 def load_traffic(name: str, kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current device code with the same kernel instantiation."""
@@ -311,6 +328,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="size sweep (one JSON line per point) instead")
     ap.add_argument("--oracle-table", action="store_true",
                     help="time the oracle at 1 thread and all cores on the small configurations instead")
+    ap.add_argument("--serve-only", type=float, default=None, metavar="RATE",
+                    help="run only the serving mix at RATE requests/s (one JSON line)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -343,6 +362,10 @@ def main():
         print(json.dumps(r), flush=True)
         return
 
+    if args.serve_only is not None:
+        print(json.dumps(serving_run(args.serve_only, args.serve_requests)), flush=True)
+        return
+
     print("[bench] primary: config2 2048^2 FP32", file=sys.stderr, flush=True)
     p = make_problem("c2", args.warmup + args.steps)
     prim = run_workload("c2", "f32", args.steps, args.warmup, p=p)
@@ -370,21 +393,11 @@ def main():
 
     serving = None
     if not args.no_serving:
-        from paper_1108_2651_amd import serve as SV
         serving = {}
         for rate in (200.0, 100.0):
             print(f"[bench] serving mix at {rate:.0f} req/s", file=sys.stderr, flush=True)
-            reqs = SV.make_requests(count=args.serve_requests, rate=rate)
-            rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=50, workers=6)
-            serving[f"{rate:.0f}_req_per_s"] = dict(
-                requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
-                p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
-                mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,
-                mean_resident=rep.mean_resident, max_resident=rep.max_resident,
-                offered_mlups=sum(r.cells * r.nsteps for r in reqs) / reqs[-1].t_arrive / 1e6)
-        serving["config"] = ("Poisson arrivals; 70% 2D 64^2-1024^2, 30% 3D 32^3-128^3; smooth eps in [1,4]; "
-                             "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 50 steps per tick; "
-                             "latency = arrival to E,B on the host")
+            serving[f"{rate:.0f}_req_per_s"] = serving_run(rate, args.serve_requests)
+        serving["config"] = SERVING_CONFIG
 
     cpu = None
     if not args.no_cpu:
