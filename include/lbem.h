@@ -271,9 +271,9 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
 
 /* Enqueue one tick on the batch stream: handle k advances by nsteps[k] steps
  * (0 <= nsteps[k] <= steps_per_tick; 0 leaves it untouched).  Members must be
- * distinct, initialised (ESTATE otherwise), created with pull streaming in a
- * format up to LBEM_BF16DEV, without a current source and with mu == 1
- * (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member
+ * distinct, initialised (ESTATE otherwise), created with pull streaming (or AA
+ * for the plain formats) in a format up to LBEM_BF16DEV, periodic, without a
+ * current source, mu == 1, and none of the cell extras (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member
  * synchronises.
  * The host-side table is double-buffered: a call waits only for the upload of
  * the tick before the previous one. */

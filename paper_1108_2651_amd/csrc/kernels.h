@@ -1164,7 +1164,8 @@ struct BatchGrid {
     int fresh;           // state in the natural layout (first step)
     int nsteps;          // steps of this lattice in this tick
     int tile_base;       // first work item of this lattice
-    int pad;
+    int aa;              // plain formats stored in place (AA pattern); fresh then
+                         // means the natural (even-step) layout at the tick start
 };
 
 struct BatchHdr {
@@ -1183,7 +1184,7 @@ __device__ __forceinline__ int batch_find(const BatchGrid* __restrict__ tab, int
     return lo;
 }
 
-template <int D, typename T, int RM>
+template <int D, typename T, int RM, int WM>
 __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, int k)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
@@ -1194,9 +1195,9 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
     const int x = tx * bx + (threadIdx.x & (bx - 1));
     const int y = ty * (NT >> g.bx_shift) + (threadIdx.x >> g.bx_shift);
     if (x >= g.nx || y >= g.ny) return;
-    const int s = (G.cur0 + k) & 1;
+    const int s = G.aa ? 0 : (G.cur0 + k) & 1;
     const T* src = (const T*)G.buf[s];
-    T* dst = (T*)G.buf[s ^ 1];
+    T* dst = (T*)G.buf[G.aa ? 0 : s ^ 1];     // AA: in place, each location read and written by one thread
     const Cell C = make_cell(g, x, y, z);
     T f[Q][P];
 #pragma unroll
@@ -1214,7 +1215,8 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int p = 0; p < P; ++p) dst[(int64_t)(i * P + p) * g.n + C.c] = out[i][p];
+        for (int p = 0; p < P; ++p)
+            dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = out[i][p];
 }
 
 template <int D, typename H, int RM>
@@ -1261,8 +1263,15 @@ __global__ __launch_bounds__(NT) void k_step_batch_plain(const BatchHdr* __restr
         const int gi = batch_find(tab, count, w);
         const BatchGrid& G = tab[gi];
         if (k >= G.nsteps) continue;
-        if (G.fresh && k == 0) batch_tile_plain<D, T, R_LOCAL>(G, w - G.tile_base, k);
-        else batch_tile_plain<D, T, R_PULL>(G, w - G.tile_base, k);
+        if (G.aa) {
+            // even steps from the natural layout, odd ones from the swapped one
+            if ((G.fresh != 0) == ((k & 1) == 0)) batch_tile_plain<D, T, R_LOCAL, W_SWAP>(G, w - G.tile_base, k);
+            else batch_tile_plain<D, T, R_PULL_SWAP, W_PUSH>(G, w - G.tile_base, k);
+        } else if (G.fresh && k == 0) {
+            batch_tile_plain<D, T, R_LOCAL, W_LOCAL>(G, w - G.tile_base, k);
+        } else {
+            batch_tile_plain<D, T, R_PULL, W_LOCAL>(G, w - G.tile_base, k);
+        }
     }
 }
 

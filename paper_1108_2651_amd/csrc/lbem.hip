@@ -1443,7 +1443,9 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
     for (int i = 0; i < count; ++i) {
         const lbem_s* h = handles[i];
         if (!h || nsteps[i] < 0 || nsteps[i] > b->ksteps) return LBEM_EINVAL;
-        if (h->nsrc != 0 || h->mu_set || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
+        if (h->nsrc != 0 || h->mu_set) return LBEM_EINVAL;
+        if (h->streaming != LBEM_STREAM_PULL && !(h->streaming == LBEM_STREAM_AA && h->prec <= LBEM_F32))
+            return LBEM_EINVAL;
         if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate kernels
         if (has_bx(h)) return LBEM_EINVAL;                // periodic boxes only
         if (!h->have_fields) return LBEM_ESTATE;
@@ -1464,8 +1466,10 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         BatchGrid& G = tab[cnt[c]++];
         std::memset(&G, 0, sizeof(G));
         if (h->prec <= LBEM_F32) {
+            const bool aa = h->streaming == LBEM_STREAM_AA;
             G.buf[0] = h->pop[0];
-            G.buf[1] = h->pop[1];
+            G.buf[1] = aa ? h->pop[0] : h->pop[1];
+            G.aa = aa;
         } else {
             const size_t moff = align256((size_t)(h->P + h->D) * h->n * 4);
             G.buf[0] = h->pop[0];
@@ -1518,8 +1522,12 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
     for (int i = 0; i < count; ++i) {
         lbem_s* h = handles[i];
         if (nsteps[i] == 0) continue;
-        if (nsteps[i] & 1) h->cur = 1 - h->cur;
-        h->layout = LAYOUT_PULL_PENDING;
+        if (h->streaming == LBEM_STREAM_AA) {
+            if (nsteps[i] & 1) h->layout = h->layout == LAYOUT_NATURAL ? LAYOUT_AA_SWAPPED : LAYOUT_NATURAL;
+        } else {
+            if (nsteps[i] & 1) h->cur = 1 - h->cur;
+            h->layout = LAYOUT_PULL_PENDING;
+        }
         h->t += nsteps[i];
     }
     return LBEM_OK;

@@ -118,6 +118,13 @@ class Report:
     latencies_ms: list = field(default_factory=list, repr=False)
 
 
+def serving_streaming(prec: str) -> str:
+    """Batched lattices step one step per launch, where the in-place AA pattern
+    of the plain formats is the faster one (and holds one copy); the 16-bit
+    formats keep pull streaming."""
+    return "aa" if prec in ("f32", "f64") else "pull"
+
+
 def bytes_per_update(dim: int, prec: str) -> int:
     Q, P = 2 * dim + 1, dim * (dim - 1) // 2
     if prec == "f32":
@@ -304,7 +311,7 @@ class GpuExecutor:
 
     def nbytes(self, r: Request) -> int:
         shape = (r.n, r.n, 1) if r.dim == 2 else (r.n, r.n, r.n)
-        return lbem.required_bytes(r.dim, shape, r.prec, streaming="pull")
+        return lbem.required_bytes(r.dim, shape, r.prec, streaming=serving_streaming(r.prec))
 
     def _stream(self):
         s = getattr(self.local, "stream", None)
@@ -318,7 +325,8 @@ class GpuExecutor:
         p = self.problem_fn(r, self)
         st = self._stream()
         with torch.cuda.stream(st):
-            s = lbem.Solver(p.dim, p.shape, r.prec, tau=p.tau, w0_vac=p.w0_vac, streaming="pull", stream=st)
+            s = lbem.Solver(p.dim, p.shape, r.prec, tau=p.tau, w0_vac=p.w0_vac,
+                            streaming=serving_streaming(r.prec), stream=st)
             s.setup(p)
         return s
 

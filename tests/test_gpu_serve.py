@@ -12,8 +12,8 @@ from paper_1108_2651_amd import inputs, lbem, serve
 pytestmark = pytest.mark.gpu
 
 
-def _solo(p, prec, nsteps):
-    s = lbem.Solver(p.dim, p.shape, prec, streaming="pull")
+def _solo(p, prec, nsteps, streaming="pull"):
+    s = lbem.Solver(p.dim, p.shape, prec, streaming=streaming)
     s.setup(p)
     s.step(nsteps)
     out = s.moments()
@@ -30,27 +30,31 @@ def test_batch_matches_standalone_bitwise(graph):
         batch = serve.Batch(16, 7, st)
     finally:
         os.environ.pop("LBEM_BATCH_GRAPH", None)
-    cases = [(2, (96, 40, 1), "f32"), (2, (33, 17, 1), "f64"), (2, (130, 64, 1), "f16dev"),
-             (3, (20, 12, 9), "f32"), (3, (16, 16, 16), "bf16dev"), (3, (9, 7, 5), "f64"),
-             (3, (24, 20, 12), "f16dev"), (2, (64, 64, 1), "bf16dev")]
+    # plain members with pull or in-place AA storage (odd step counts leave AA
+    # lattices in the swapped layout between ticks)
+    cases = [(2, (96, 40, 1), "f32", "pull"), (2, (33, 17, 1), "f64", "pull"), (2, (130, 64, 1), "f16dev", "pull"),
+             (3, (20, 12, 9), "f32", "pull"), (3, (16, 16, 16), "bf16dev", "pull"), (3, (9, 7, 5), "f64", "aa"),
+             (3, (24, 20, 12), "f16dev", "pull"), (2, (64, 64, 1), "bf16dev", "pull"), (2, (70, 30, 1), "f32", "aa"),
+             (3, (17, 13, 11), "f32", "aa"), (2, (40, 24, 1), "f64", "aa")]
     probs, solvers = [], []
     other = torch.cuda.Stream()
-    for k, (dim, shape, prec) in enumerate(cases):
+    for k, (dim, shape, prec, streaming) in enumerate(cases):
         p = random_problem(dim, shape, seed=200 + k, src=False)
         # half of the members live on another stream than the batch
-        s = lbem.Solver(dim, shape, prec, streaming="pull", stream=st if k % 2 == 0 else other)
+        s = lbem.Solver(dim, shape, prec, streaming=streaming, stream=st if k % 2 == 0 else other)
         s.setup(p)
         probs.append(p)
         solvers.append(s)
-    plan = [[7, 3, 7, 0, 5, 7, 1, 7], [7, 7, 0, 7, 7, 2, 7, 7], [1, 7, 7, 7, 0, 7, 7, 4]]
+    plan = [[7, 3, 7, 0, 5, 7, 1, 7, 3, 5, 7], [7, 7, 0, 7, 7, 2, 7, 7, 7, 0, 1],
+            [1, 7, 7, 7, 0, 7, 7, 4, 5, 7, 2]]
     total = np.sum(plan, axis=0)
     for ns in plan:
         batch.run(solvers, ns)
-    for k, (dim, shape, prec) in enumerate(cases):
-        announce(f"batch vs solo graph={graph} {dim}d {shape} {prec} steps={total[k]}")
+    for k, (dim, shape, prec, streaming) in enumerate(cases):
+        announce(f"batch vs solo graph={graph} {dim}d {shape} {prec} {streaming} steps={total[k]}")
         got = solvers[k].moments()
         assert solvers[k].t == total[k]
-        want = _solo(probs[k], prec, int(total[k]))
+        want = _solo(probs[k], prec, int(total[k]), streaming)
         assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
     for s in solvers:
         s.close()
