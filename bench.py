@@ -45,6 +45,8 @@ def bytes_per_cell(dim: int, prec: str, mu: bool = False) -> int:
         return 2 * Q * P * 8 + 8 + extra
     if prec == "f32":
         return 2 * Q * P * 4 + 4 + extra
+    if prec == "f16":
+        return 2 * Q * P * 2 + 4 + extra
     slots = (Q - 1) * P - dim if "ghost" in prec else Q * P
     return 2 * ((P + dim) * 4 + slots * 2) + 4 + extra
 
@@ -255,11 +257,12 @@ def cpu_baseline_table(budget_s: float = 4.0) -> list:
 
 def size_sweep(steps: int = 100, warmup: int = 5) -> list:
     """Roofline sweep across the Infinity-Cache boundary: 3D spheres medium
-    from 64^3 to 512^3 in FP32 (pull, fused pair; AA single steps) and the
-    two 16-bit formats; 2D from 512^2 to 8192^2 in FP32."""
+    from 64^3 to 512^3 in FP32 (pull, fused pair; AA single steps), plain
+    FP16 storage (AA single steps) and the two 16-bit deviation formats; 2D
+    from 512^2 to 8192^2 in FP32."""
     rows = []
     plan = [(f"3d{n}", prec, st) for n in (64, 96, 128, 160, 192, 256, 320, 384, 448, 512)
-            for prec, st in (("f32", "pull"), ("f32", "aa"), ("f16dev", "pull"), ("f16ghost", "pull"))]
+            for prec, st in (("f32", "pull"), ("f32", "aa"), ("f16", "aa"), ("f16dev", "pull"), ("f16ghost", "pull"))]
     plan += [(f"2d{n}", "f32", st) for n in (512, 1024, 2048, 4096, 8192) for st in ("pull", "aa")]
     for name, prec, st in plan:
         n = int(name[2:])
@@ -378,12 +381,11 @@ def main():
                 ("c3", "f16dev", "pull", 200, 10), ("c3", "bf16dev", "pull", 200, 10),
                 ("c3", "f16ghost", "pull", 200, 10),
                 ("c4", "f32", "pull", 50, 6), ("c4", "f32", "aa", 50, 5), ("c4", "f16dev", "pull", 50, 5),
-                ("c4", "f16ghost", "pull", 50, 5),
+                ("c4", "f16ghost", "pull", 50, 5), ("c3", "f16", "aa", 200, 10), ("c4", "f16", "aa", 50, 5),
                 ("c2mu", "f32", "pull", 1000, 20), ("c3mu", "f32", "auto", 200, 10),
                 ("c3mu", "f16ghost", "pull", 200, 10), ("c2walls", "f32", "pull", 1000, 20),
                 ("c3disp", "f32", "pull", 200, 10), ("c3disp", "f16ghost", "pull", 200, 10),
                 ("c3aniso", "f32", "pull", 200, 10)]
-        plan = [(a, b, c, k, w) for a, b, c, k, w in plan]
         for name, prec, st, k, w in plan:
             print(f"[bench] variant {name} {prec} {st}", file=sys.stderr, flush=True)
             try:

@@ -62,7 +62,12 @@ typedef enum {
                           (Q-1)P - D moving deviations that the zero-moment
                           constraints leave free are stored (2D 2 of 5, 3D 15 of
                           21 per cell); the rest follow from the constraints    */
-    LBEM_BF16GHOST = 5 /* as LBEM_F16GHOST with BF16 ghost coordinates           */
+    LBEM_BF16GHOST = 5, /* as LBEM_F16GHOST with BF16 ghost coordinates          */
+    LBEM_F16 = 6       /* plain FP16 populations, FP32 medium and arithmetic
+                          (rounded to nearest on store); single steps, pull or
+                          AA.  A bandwidth reference: its rounding is relative
+                          to the whole population, so it misses the 1e-3 bar
+                          the deviation formats meet                            */
 } lbem_prec;
 
 /* Kind of the two faces of one axis (lbem_set_boundary). */

@@ -378,8 +378,20 @@ __device__ __forceinline__ bool stage_source(const SrcArgs<T>& s, int b, T* lds)
 // ---------------------------------------------------------------------------
 // plain FP64/FP32 stream-collide
 // ---------------------------------------------------------------------------
-template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX>
-__global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T* __restrict__ cl2a,
+// Storage <-> arithmetic of the plain formats: populations are stored as S
+// and computed in T (S = T except plain FP16 storage with FP32 arithmetic,
+// rounded to nearest even on the store).
+template <typename T, typename S>
+__device__ __forceinline__ T ld_pop(S v) { return (T)v; }
+template <>
+__device__ __forceinline__ float ld_pop<float, __half>(__half v) { return __half2float(v); }
+template <typename S, typename T>
+__device__ __forceinline__ S st_pop(T v) { return (S)v; }
+template <>
+__device__ __forceinline__ __half st_pop<__half, float>(float v) { return __float2half_rn(v); }
+
+template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX, typename S = T>
+__global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T* __restrict__ cl2a,
                                                   const T* __restrict__ dlnmu, const Geo g,
                                                   const SrcArgs<T> s, const T omega, const int tau_half,
                                                   const CellExt bc)
@@ -401,10 +413,10 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (BX && RM == R_PULL && ((C.wall >> i) & 1u)) {
-                    const T v = src[(int64_t)(opp(D, i) * P + p) * g.n + C.c];
+                    const T v = ld_pop<T>(src[(int64_t)(opp(D, i) * P + p) * g.n + C.c]);
                     f[i][p] = wall_negates<D>(bc, i, p) ? -v : v;
                 } else {
-                    f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+                    f[i][p] = ld_pop<T>(src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]);
                 }
             }
         const T cl2 = cl2a[C.c];
@@ -445,7 +457,7 @@ __global__ __launch_bounds__(NT) void k_step_plain(const T* src, T* dst, const T
         for (int i = 0; i < Q; ++i)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = out[i][p];
+                dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = st_pop<S>(out[i][p]);
     }
 }
 
@@ -1292,19 +1304,20 @@ __global__ __launch_bounds__(NT) void k_step_batch_dev(const BatchHdr* __restric
 // ---------------------------------------------------------------------------
 // readers for the field / diagnostic kernels
 // ---------------------------------------------------------------------------
-template <int D, typename T, int RM>
+template <int D, typename S, int RM>
 struct PlainReader {
-    const T* pop;
+    const S* pop;
     int64_t n;
     CellExt bc;
     static constexpr bool PULL = RM == R_PULL;
+    using Wide = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
     __device__ __forceinline__ double get(const Cell& C, int i, int p, double) const
     {
         if (PULL && ((C.wall >> i) & 1u)) {
-            const double v = (double)pop[(int64_t)(opp(D, i) * Lat<D>::P + p) * n + C.c];
+            const double v = (double)ld_pop<Wide>(pop[(int64_t)(opp(D, i) * Lat<D>::P + p) * n + C.c]);
             return wall_negates<D>(bc, i, p) ? -v : v;
         }
-        return (double)pop[(int64_t)(read_slot<D, RM>(i) * Lat<D>::P + p) * n + read_cell<D, RM>(C, i)];
+        return (double)ld_pop<Wide>(pop[(int64_t)(read_slot<D, RM>(i) * Lat<D>::P + p) * n + read_cell<D, RM>(C, i)]);
     }
 };
 
@@ -1562,9 +1575,9 @@ __global__ __launch_bounds__(NT) void k_aniso(const double* __restrict__ fac, in
     cl2[c] = (TM)cbar;
 }
 
-template <int D, typename T>
+template <int D, typename T, typename S = T>
 __global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E, const double* __restrict__ B,
-                                                   const T* __restrict__ cl2a, int64_t n, T* pop,
+                                                   const T* __restrict__ cl2a, int64_t n, S* pop,
                                                    const T* __restrict__ ra)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
@@ -1577,7 +1590,7 @@ __global__ __launch_bounds__(NT) void k_init_plain(const double* __restrict__ E,
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-        for (int p = 0; p < P; ++p) pop[(int64_t)(i * P + p) * n + c] = (T)g0[i][p];
+        for (int p = 0; p < P; ++p) pop[(int64_t)(i * P + p) * n + c] = st_pop<S>((T)g0[i][p]);
 }
 
 template <int D, typename H, bool GH>

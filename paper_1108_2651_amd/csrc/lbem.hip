@@ -35,11 +35,14 @@ struct Sizes {
     size_t total;
 };
 
+// the formats with FP32 moments + 16-bit deviations or ghost coordinates
+bool is_dev(int prec) { return prec >= LBEM_F16DEV && prec <= LBEM_BF16GHOST; }
+
 bool valid_cfg(const lbem_config* c)
 {
     if (!c) return false;
     if (c->dim != 2 && c->dim != 3) return false;
-    if (c->prec < LBEM_F64 || c->prec > LBEM_BF16GHOST) return false;
+    if (c->prec < LBEM_F64 || c->prec > LBEM_F16) return false;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return false;
     if (c->dim == 2 && c->nz != 1) return false;
     if (c->nx > (1 << 30) || c->ny > (1 << 30) || c->nz > (1 << 30)) return false;
@@ -48,7 +51,7 @@ bool valid_cfg(const lbem_config* c)
     if (!(c->tau > 0.0) || !std::isfinite(c->tau)) return false;
     if (!(c->w0_vac >= 0.0 && c->w0_vac < 1.0)) return false;
     if (c->streaming < LBEM_STREAM_AUTO || c->streaming > LBEM_STREAM_AA) return false;
-    if (c->streaming == LBEM_STREAM_AA && c->prec >= LBEM_F16DEV) return false;
+    if (c->streaming == LBEM_STREAM_AA && is_dev(c->prec)) return false;
     return true;
 }
 
@@ -74,8 +77,8 @@ Sizes sizes_of(const lbem_config* c)
     const int D = c->dim, Q = 2 * D + 1, P = D * (D - 1) / 2;
     const size_t n = (size_t)(c->nx * c->ny * c->nz);
     const size_t tm = c->prec == LBEM_F64 ? 8 : 4;
-    if (c->prec <= LBEM_F32)
-        s.pop_one = align256((size_t)Q * P * n * tm);
+    if (!is_dev(c->prec))
+        s.pop_one = align256((size_t)Q * P * n * (c->prec == LBEM_F16 ? 2 : tm));
     else
         s.pop_one = align256((size_t)(P + D) * n * 4) +
                     align256((size_t)(c->prec >= LBEM_F16GHOST ? 2 * D * P - D : Q * P) * n * 2);
@@ -298,10 +301,11 @@ static bool fused_ok(const lbem_s* h)
     return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1 && !has_bx(h);
 }
 
-template <int D, typename T>
+// plain formats: populations stored as S, arithmetic in T
+template <int D, typename T, typename S = T>
 struct PlainImpl : Impl {
     template <int RM, int WM, int V, bool MU, bool BX = false>
-    static hipError_t go(lbem_s* h, const T* src, T* dst, T amp)
+    static hipError_t go(lbem_s* h, const S* src, S* dst, T amp)
     {
         SrcArgs<T> s;
         s.off = h->nsrc ? h->src_off : nullptr;
@@ -309,13 +313,13 @@ struct PlainImpl : Impl {
         s.val = (const T*)h->src_val;
         s.amp = amp;
         const double om = 1.0 / h->cfg.tau;
-        hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
+        hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX, S>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
                            (int)(h->cfg.tau == 0.5), ext_of(h));
         return hipGetLastError();
     }
     template <int RM, int WM>
-    static hipError_t go_v(lbem_s* h, const T* src, T* dst, T amp)
+    static hipError_t go_v(lbem_s* h, const S* src, S* dst, T amp)
     {
         if constexpr (WM == W_LOCAL && RM != R_PULL_SWAP) {
             if (has_bx(h)) {   // pull streaming only (AA is refused with walls or an absorber)
@@ -334,7 +338,7 @@ struct PlainImpl : Impl {
     }
     hipError_t step(lbem_s* h, double amp) override
     {
-        T* a = (T*)h->pop[h->cur];
+        S* a = (S*)h->pop[h->cur];
         if (h->streaming == LBEM_STREAM_AA) {
             hipError_t e;
             if (h->layout == LAYOUT_NATURAL) {
@@ -346,7 +350,7 @@ struct PlainImpl : Impl {
             }
             return e;
         }
-        T* b = (T*)h->pop[1 - h->cur];
+        S* b = (S*)h->pop[1 - h->cur];
         hipError_t e = h->layout == LAYOUT_NATURAL ? go_v<R_LOCAL, W_LOCAL>(h, a, b, (T)amp)
                                                    : go_v<R_PULL, W_LOCAL>(h, a, b, (T)amp);
         h->cur = 1 - h->cur;
@@ -355,30 +359,34 @@ struct PlainImpl : Impl {
     }
     hipError_t step_fused(lbem_s* h, const double* amp) override
     {
-        const T* a = (const T*)h->pop[h->cur];
-        T* b = (T*)h->pop[1 - h->cur];
-        hipError_t e;
-        if constexpr (D == 2) e = go_fused<T>(h, a, b, amp);
-        else e = go_fused3<T>(h, a, b, amp);
-        h->cur = 1 - h->cur;
-        return e;
+        if constexpr (!std::is_same<S, T>::value) {
+            return hipErrorInvalidValue;   // the multi-step kernels keep FP64/FP32 storage
+        } else {
+            const T* a = (const T*)h->pop[h->cur];
+            T* b = (T*)h->pop[1 - h->cur];
+            hipError_t e;
+            if constexpr (D == 2) e = go_fused<T>(h, a, b, amp);
+            else e = go_fused3<T>(h, a, b, amp);
+            h->cur = 1 - h->cur;
+            return e;
+        }
     }
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
-        const T* a = (const T*)h->pop[h->cur];
+        const S* a = (const S*)h->pop[h->cur];
         const CellExt bc = ext_of(h);
         if (h->layout == LAYOUT_NATURAL)
-            return launch_fields<D, T>(h, PlainReader<D, T, R_LOCAL>{a, h->n, bc}, E, B, partials);
+            return launch_fields<D, T>(h, PlainReader<D, S, R_LOCAL>{a, h->n, bc}, E, B, partials);
         if (h->layout == LAYOUT_PULL_PENDING)
-            return launch_fields<D, T>(h, PlainReader<D, T, R_PULL>{a, h->n, bc}, E, B, partials);
-        return launch_fields<D, T>(h, PlainReader<D, T, R_PULL_SWAP>{a, h->n, bc}, E, B, partials);
+            return launch_fields<D, T>(h, PlainReader<D, S, R_PULL>{a, h->n, bc}, E, B, partials);
+        return launch_fields<D, T>(h, PlainReader<D, S, R_PULL_SWAP>{a, h->n, bc}, E, B, partials);
     }
     hipError_t init(lbem_s* h, const double* dE, const double* dB) override
     {
         h->cur = 0;
         h->layout = LAYOUT_NATURAL;
-        hipLaunchKernelGGL((k_init_plain<D, T>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
-                           (const T*)h->cl2, h->n, (T*)h->pop[0], (const T*)(h->ra_set ? h->ra : nullptr));
+        hipLaunchKernelGGL((k_init_plain<D, T, S>), dim3(blocks1(h->n)), dim3(NT), 0, h->stream, dE, dB,
+                           (const T*)h->cl2, h->n, (S*)h->pop[0], (const T*)(h->ra_set ? h->ra : nullptr));
         return hipGetLastError();
     }
     hipError_t medium(lbem_s* h, const double* deps, const double* dmu, int* dflag) override
@@ -476,6 +484,7 @@ static Impl* make_impl(int D, int prec)
         switch (prec) {
             case LBEM_F64: return new (std::nothrow) PlainImpl<2, double>();
             case LBEM_F32: return new (std::nothrow) PlainImpl<2, float>();
+            case LBEM_F16: return new (std::nothrow) PlainImpl<2, float, __half>();
             case LBEM_F16DEV: return new (std::nothrow) DevImpl<2, __half, false>();
             case LBEM_BF16DEV: return new (std::nothrow) DevImpl<2, __hip_bfloat16, false>();
             case LBEM_F16GHOST: return new (std::nothrow) DevImpl<2, __half, true>();
@@ -485,6 +494,7 @@ static Impl* make_impl(int D, int prec)
     switch (prec) {
         case LBEM_F64: return new (std::nothrow) PlainImpl<3, double>();
         case LBEM_F32: return new (std::nothrow) PlainImpl<3, float>();
+        case LBEM_F16: return new (std::nothrow) PlainImpl<3, float, __half>();
         case LBEM_F16DEV: return new (std::nothrow) DevImpl<3, __half, false>();
         case LBEM_BF16DEV: return new (std::nothrow) DevImpl<3, __hip_bfloat16, false>();
         case LBEM_F16GHOST: return new (std::nothrow) DevImpl<3, __half, true>();
@@ -508,7 +518,7 @@ static void make_geo(lbem_s* h)
     g.nblocks = g.tiles_x * g.tiles_y * nz;
     // measured defaults: XCD-contiguous tile ranges help 2D, not 3D AA
     g.xcd = env_int("LBEM_XCD", h->D == 2 ? 1 : 0);
-    const int sdef = (h->D == 3 && h->prec >= LBEM_F16DEV) ? 32 : 0;
+    const int sdef = (h->D == 3 && is_dev(h->prec)) ? 32 : 0;
     g.strip = env_int("LBEM_STRIP", sdef);
     if (g.strip <= 0 || nz == 1 || g.strip >= g.tiles_y || g.tiles_y % g.strip != 0) g.strip = 0;
 }
@@ -568,7 +578,7 @@ static void make_fused_geo(lbem_s* h)
 
 static void make_zmarch_geo(lbem_s* h)
 {
-    h->zmarch = (h->D == 3 && h->prec >= LBEM_F16DEV) ? env_int("LBEM_DEV3Z", (double)h->n >= SMALL3D) : 0;
+    h->zmarch = (h->D == 3 && is_dev(h->prec)) ? env_int("LBEM_DEV3Z", (double)h->n >= SMALL3D) : 0;
     h->zlz = std::max(1, env_int("LBEM_DEV3Z_LZ", 16));
     Geo& g = h->zgeo;
     g = h->geo;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "_build", "liblbem.so")
 
 LBEM_OK, LBEM_EINVAL, LBEM_ENOMEM, LBEM_EUNSTABLE, LBEM_ENONFINITE, LBEM_EDEVICE, LBEM_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
-PREC = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3, "f16ghost": 4, "bf16ghost": 5}
+PREC = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3, "f16ghost": 4, "bf16ghost": 5, "f16": 6}
 STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 
 # every entry point of include/lbem.h

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1108_2651_amd import lbem
@@ -54,12 +55,18 @@ def test_strerror_and_required_bytes():
     assert bd - bg == 2 * 6 * 2 * m
     assert (lbem.required_bytes(2, (256, 256, 1), "f16dev") -
             lbem.required_bytes(2, (256, 256, 1), "f16ghost")) == 2 * 3 * 2 * 256 * 256
+    # plain FP16 storage: the FP32 layout at half the population bytes (AA: one copy)
+    for dim, shape in ((2, (256, 256, 1)), (3, (64, 64, 64))):
+        n, QP = int(np.prod(shape)), (5 if dim == 2 else 21)
+        for st, copies in (("pull", 2), ("aa", 1)):
+            assert (lbem.required_bytes(dim, shape, "f32", streaming=st) -
+                    lbem.required_bytes(dim, shape, "f16", streaming=st)) == copies * QP * 2 * n
 
 
 @pytest.mark.parametrize("kw", [dict(dim=4), dict(dim=2, shape=(8, 8, 2)), dict(prec="f64", tau=0.0),
                                 dict(w0_vac=1.0), dict(w0_vac=-0.1), dict(shape=(0, 4, 1)),
                                 dict(prec="f16dev", streaming="aa"), dict(prec="f16ghost", streaming="aa"),
-                                dict(prec=6), dict(shape=(2048, 2048, 1024), dim=3)])
+                                dict(prec=7), dict(prec=-1), dict(shape=(2048, 2048, 1024), dim=3)])
 def test_invalid_configs_rejected_on_host(kw):
     args = dict(dim=2, shape=(8, 8, 1), prec="f32")
     args.update(kw)

@@ -19,6 +19,8 @@ def test_bytes_per_cell_counts_every_stored_value_once_each_way():
     assert bench.bytes_per_cell(2, "f32") == 2 * 5 * 4 + 4 == 44
     assert bench.bytes_per_cell(3, "f32") == 2 * 21 * 4 + 4 == 172
     assert bench.bytes_per_cell(2, "f64") == 88 and bench.bytes_per_cell(3, "f64") == 344
+    # plain FP16 storage: FP16 populations, FP32 medium
+    assert bench.bytes_per_cell(2, "f16") == 2 * 5 * 2 + 4 == 24 and bench.bytes_per_cell(3, "f16") == 88
     # deviation storage: (P + D) FP32 moments + Q*P halves
     assert bench.bytes_per_cell(2, "f16dev") == 2 * (3 * 4 + 5 * 2) + 4 == 48
     assert bench.bytes_per_cell(3, "bf16dev") == 2 * (6 * 4 + 21 * 2) + 4 == 136
