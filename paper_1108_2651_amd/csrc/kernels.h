@@ -970,6 +970,55 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
         }
 }
 
+// Collide and encode in one pass (deviation formats, no cell extras).  The
+// collision takes a state g with moments m = (Lambda, Bbar) to
+// (1 - omega) g + omega g0(m) + T, and the source term T has the shape of an
+// equilibrium: it moves each pair moment Lambda_p by -Sp_p and leaves K as it
+// is.  The new moments are therefore (Lambda - Sp, Bbar), and the deviation of
+// the new state from their equilibrium is (1 - omega)(g - g0(m)) exactly.
+// Only that product is rounded; the post-collision populations are never
+// formed and their moments never summed again.
+template <int D, typename H, bool GH>
+__device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
+                                                  const float (&Sp)[Lat<D>::P], bool any_src, float omega,
+                                                  bool tau_half, const float (&rho)[Lat<D>::P],
+                                                  const float (&K)[D], int64_t n, int c, float* Mout, H* Dout)
+{
+    constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
+    float Lam[P], Bb[D];
+#pragma unroll
+    for (int p = 0; p < P; ++p) Lam[p] = cl2 * rho[p];
+#pragma unroll
+    for (int b = 0; b < D; ++b) Bb[b] = D == 2 ? K[b] : 0.5f * K[b];
+    float m = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const float l2 = any_src ? Lam[p] - Sp[p] : Lam[p];
+        Mout[(int64_t)p * n + c] = l2;
+        m = fmaxf(m, fabsf(l2));
+    }
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        Mout[(int64_t)(P + b) * n + c] = Bb[b];
+        m = fmaxf(m, fabsf(Bb[b]));
+    }
+    float s, inv;
+    pow2_scale(m, s, inv);
+    const float f1 = tau_half ? -1.f : 1.f - omega;
+    const float km = f1 * (2.f * inv);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int sl = dev_slot<D, GH>(i, p);
+            if (sl < 0) continue;
+            float code;
+            if (i == 0) code = (f[0][p] - (rho[p] - float(D) * Lam[p])) * (f1 * (inv / wc0));
+            else code = (f[i][p] - 0.5f * twice_eq_moving<D, float>(i, p, Lam[p], Bb)) * km;
+            Dout[(int64_t)sl * n + c] = f2h<H>(sat16<H>(code));
+        }
+}
+
 template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
@@ -1011,23 +1060,28 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
             for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
             add_mu_source<D, float>(K, cl2, dl, Sp);
         }
-        float Jn[P];
-        const bool ade = BX && bc.ade != nullptr;
-        if (ade) ade_update<D, float>(bc, g.n, C.c, cl2, rho, Jn);
-        float out[Q][P];
-        collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-        if (ade) {
+        if constexpr (!BX) {
+            dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c, Mout,
+                                        Dout);
+        } else {
+            float Jn[P];
+            const bool ade = bc.ade != nullptr;
+            if (ade) ade_update<D, float>(bc, g.n, C.c, cl2, rho, Jn);
+            float out[Q][P];
+            collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+            if (ade) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
+                for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
+            }
+            if (bc.keep) {
+                const float k = ((const float*)bc.keep)[C.c];
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) out[i][p] *= k;
+            }
+            dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
         }
-        if (BX && bc.keep) {
-            const float k = ((const float*)bc.keep)[C.c];
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-#pragma unroll
-                for (int p = 0; p < P; ++p) out[i][p] *= k;
-        }
-        dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
     }
 }
 
@@ -1072,21 +1126,45 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
     const bool has_src = s1 > s0;
     const bool any_src = has_src || MU;
 
-    auto load_plane = [&](int zz, int q) {
+    // in-plane cells of the window entries this thread loads (the same in
+    // every plane; periodic images wrapped once here)
+    constexpr int KW = (PC + NT - 1) / NT;
+    int off2d[KW];
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+        const int k = threadIdx.x + j * NT;
+        const int hx = k % W, hy = k / W;
+        int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
+        if (gx < 0) gx += g.nx;
+        if (gy < 0) gy += g.ny;
+        off2d[j] = gx + g.nx * gy;
+    }
+    const int nxy = g.nx * g.ny;
+    // Window planes are fetched one iteration ahead into registers, so their
+    // loads are in flight while the previous plane is updated.
+    float pre[KW][NM];
+    auto fetch_plane = [&](int zz) {
         zz %= g.nz;
         if (zz < 0) zz += g.nz;
-        for (int k = threadIdx.x; k < PC; k += NT) {
-            const int hx = k % W, hy = k / W;
-            int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
-            if (gx < 0) gx += g.nx;
-            if (gy < 0) gy += g.ny;
-            const int c = gx + g.nx * (gy + g.ny * zz);
+        const int64_t zoff = (int64_t)zz * nxy;
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+            if (threadIdx.x + j * NT >= PC) break;
+            const int64_t c = zoff + off2d[j];
+#pragma unroll
+            for (int t = 0; t < NM; ++t) pre[j][t] = Min[(int64_t)t * g.n + c];
+        }
+    };
+    auto stash_plane = [&](int q) {
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+            const int k = threadIdx.x + j * NT;
+            if (k >= PC) break;
             float m = 0.f;
 #pragma unroll
             for (int t = 0; t < NM; ++t) {
-                const float v = Min[(int64_t)t * g.n + c];
-                lm[q][t][k] = v;
-                m = fmaxf(m, fabsf(v));
+                lm[q][t][k] = pre[j][t];
+                m = fmaxf(m, fabsf(pre[j][t]));
             }
             float sv, iv;
             pow2_scale(m, sv, iv);
@@ -1094,12 +1172,16 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
         }
     };
 
-    load_plane(z0 - 1, 0);
-    load_plane(z0, 1);
+    fetch_plane(z0 - 1);
+    stash_plane(0);
+    fetch_plane(z0);
+    stash_plane(1);
+    fetch_plane(z0 + 1);
     for (int z = z0; z < z1; ++z) {
         const int rel = z - z0;
         const int qm = rel % 3, qc = (rel + 1) % 3, qp = (rel + 2) % 3;
-        load_plane(z + 1, qp);
+        stash_plane(qp);                       // plane z + 1
+        if (z + 1 < z1) fetch_plane(z + 2);    // lands during this plane's update
         if (has_src) {
             for (int k = threadIdx.x; k < P * NT; k += NT) lsrc[k] = 0.f;
             __syncthreads();
@@ -1149,9 +1231,8 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
                 for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
                 add_mu_source<D, float>(K, cl2, dl, Sp);
             }
-            float out[Q][P];
-            collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
-            dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+            dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c, Mout,
+                                        Dout);
         }
         __syncthreads();
     }
@@ -1260,9 +1341,8 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
     moments<D, float>(f, rho, K);
 #pragma unroll
     for (int p = 0; p < P; ++p) Sp[p] = 0.f;
-    float out[Q][P];
-    collide<D, float>(f, cl2, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, out);
-    dev_store<D, H, false>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+    dev_collide_store<D, H, false>(f, cl2, wc0, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, g.n, C.c,
+                                   Mout, Dout);
 }
 
 // Launch k of a tick: every lattice with k < nsteps advances one step.
