@@ -23,11 +23,15 @@ _lib = None
 
 
 def lib():
+    """The oracle library.  LBEM_ORACLE_LIB names another build of the same
+    source (the tests that plant mistakes in the oracle load their mutants
+    this way); by default the in-tree build, compiled on first use."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("LBEM_ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.c_int, C.c_long, C.c_long, C.c_long, C.c_double, C.c_double]

@@ -199,6 +199,25 @@ def test_uniform_current_closed_form(dim, shape, comp):
     np.testing.assert_allclose(g[0], proj(dim, w0, g[0]), rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("dim,shape,comp", [(2, (6, 5, 1), 2), (3, (4, 3, 4), 1)])
+def test_uniform_current_follows_the_amplitude_series(dim, shape, comp):
+    # the current of step t enters that step (source time level): after the
+    # steps t0..t1-1 of one call, E has moved by -sum(amp[t0:t1]) j / eps_abs
+    n = int(np.prod(shape))
+    eps_r, w0_vac, j = 3.0, 1.0 / 3.0, 0.4
+    o = O.Oracle(dim, shape, 0.5, w0_vac)
+    o.set_medium(np.full(n, eps_r))
+    o.init_fields(np.zeros((3, n)), np.zeros((3, n)))
+    o.set_source(comp, np.arange(n), np.full(n, j))
+    eps_abs = eps_r / ((1 - w0_vac) / (dim * (dim - 1)))
+    amp = np.random.default_rng(5).standard_normal(20)
+    for t0, t1 in ((0, 7), (7, 20)):
+        o.step(t1 - t0, amp[t0:t1])
+        E, B = o.fields()
+        np.testing.assert_allclose(E[comp], -amp[:t1].sum() * j / eps_abs, rtol=1e-12)
+        assert np.abs(B).max() < 1e-14
+
+
 def test_medium_stability_bounds():
     o = O.Oracle(2, (4, 4, 1), 0.5, 1.0 / 3.0)
     # eps_r * mu_r < 1 - w0_vac gives w0 < 0: rejected

@@ -320,23 +320,26 @@ def test_energy_bounded_c1():
         assert abs(d["energy"] / e0 - 1) < 3e-3
 
 
-def test_matched_impedance_slab_does_not_reflect():
+@pytest.mark.parametrize("dim,steps", [(2, 330), (3, 570)])
+def test_matched_impedance_slab_does_not_reflect(dim, steps):
+    # in 3D the mu term carries c_M^2 = c_L^2/2: c_L^2 there would double it
+    # and the eps = mu slab would no longer be impedance matched
     nx = 512
     x = np.arange(nx)
     ramp = 0.5 * (np.tanh((x - 200) / 4.0) - np.tanh((x - 400) / 4.0))
-    cv = inputs.vacuum_speed(2, 1.0 / 3.0)
+    cv = inputs.vacuum_speed(dim, 1.0 / 3.0)
     E0 = np.zeros((3, nx)); B0 = np.zeros((3, nx))
     f = np.exp(-(x - 100.0) ** 2 / (2 * 8.0 ** 2))
     E0[2] = f
     B0[1] = -f / cv                                     # right-moving pulse
     refl = {}
     for name, eps, mu in (("unmatched", 1 + 3 * ramp, None), ("matched", 1 + ramp, 1 + ramp)):
-        o = O.Oracle(2, (nx, 1, 1))
+        o = O.Oracle(dim, (nx, 1, 1))
         o.set_medium(eps, mu)
         o.init_fields(E0, B0)
         e0 = o.diag()["energy"]
         med = o.medium()
-        o.step(330)
+        o.step(steps)
         E, B = o.fields()
         dens = med["eps_abs"] * E[2] ** 2 + (B[0] ** 2 + B[1] ** 2) / (1 if mu is None else mu)
         refl[name] = dens[:180].sum() / e0
