@@ -1456,7 +1456,7 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         if (h->nsrc != 0 || h->mu_set) return LBEM_EINVAL;
         if (h->streaming != LBEM_STREAM_PULL && !(h->streaming == LBEM_STREAM_AA && h->prec <= LBEM_F32))
             return LBEM_EINVAL;
-        if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate kernels
+        if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate or plain FP16 kernels
         if (has_bx(h)) return LBEM_EINVAL;                // periodic boxes only
         if (!h->have_fields) return LBEM_ESTATE;
         for (int j = 0; j < i; ++j)
