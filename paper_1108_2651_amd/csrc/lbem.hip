@@ -1321,7 +1321,7 @@ int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int NCLASS = 8;  // (dim - 2) * 4 + prec
-constexpr int BATCH_BLOCKS = 1024;
+constexpr int BATCH_BLOCKS = 8192;  // persistent grid (more blocks than fit: the rest start as others finish)
 
 int class_of(const lbem_s* h) { return (h->D - 2) * 4 + h->prec; }
 
@@ -1339,6 +1339,7 @@ struct lbem_batch_s {
     std::vector<std::pair<unsigned, hipGraphExec_t>> graphs;
     std::vector<hipGraph_t> raw;
     int use_graph;
+    int blocks;                // persistent grid of each class launch
     hipEvent_t tick_ev;        // end of the last enqueued tick
 };
 
@@ -1347,7 +1348,7 @@ static void launch_class(lbem_batch_s* b, int c, int k)
     const size_t cb = class_bytes(b->max_grids);
     const BatchHdr* hdr = (const BatchHdr*)(b->dev + c * cb);
     const BatchGrid* tab = (const BatchGrid*)(b->dev + c * cb + align256(sizeof(BatchHdr)));
-    dim3 g(BATCH_BLOCKS), t(NT);
+    dim3 g(b->blocks), t(NT);
     switch (c) {
         case 0: hipLaunchKernelGGL((k_step_batch_plain<2, double>), g, t, 0, b->stream, hdr, tab, k); break;
         case 1: hipLaunchKernelGGL((k_step_batch_plain<2, float>), g, t, 0, b->stream, hdr, tab, k); break;
@@ -1406,6 +1407,7 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     b->ksteps = steps_per_tick;
     b->ring = 0;
     b->use_graph = env_int("LBEM_BATCH_GRAPH", 1);
+    b->blocks = std::max(1, env_int("LBEM_BATCH_BLOCKS", BATCH_BLOCKS));
     const size_t bytes = class_bytes(max_lattices) * NCLASS;
     b->dev = nullptr;
     b->pinned[0] = b->pinned[1] = nullptr;
