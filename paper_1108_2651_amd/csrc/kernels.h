@@ -878,14 +878,15 @@ struct DevSlots {
     static constexpr int N = GH ? 2 * D * Lat<D>::P - D : Lat<D>::Q * Lat<D>::P;
 };
 
-// scaled code of moving entry (i,p) at cell cs: stored, or recovered from its
-// first-moment constraint
-template <int D, typename H, bool GH>
-__device__ __forceinline__ float dev_code(const H* Dv, int64_t n, int i, int p, int cs)
+// scaled code of moving entry (i,p) of one cell: stored, or recovered from its
+// first-moment constraint; get(slot) returns the cell's stored code of a slot
+// (read from HBM or held in registers: the arithmetic is the same)
+template <int D, bool GH, class Get>
+__device__ __forceinline__ float dev_code_of(const Get& get, int i, int p)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     const int e = GH ? ghost_dropped_by(D, i, p) : -1;
-    if (e < 0) return h2f<H>(Dv[(int64_t)dev_slot<D, GH>(i, p) * n + cs]);
+    if (e < 0) return get(dev_slot<D, GH>(i, p));
     float sum = 0.f;
 #pragma unroll
     for (int j = 1; j < Q; ++j)
@@ -893,23 +894,31 @@ __device__ __forceinline__ float dev_code(const H* Dv, int64_t n, int i, int p, 
         for (int q = 0; q < P; ++q) {
             const int k = kcoef(D, j, q, e);
             if (k == 0 || (j == i && q == p)) continue;
-            const float v = h2f<H>(Dv[(int64_t)dev_slot<D, GH>(j, q) * n + cs]);
+            const float v = get(dev_slot<D, GH>(j, q));
             sum = k > 0 ? sum + v : sum - v;
         }
     return kcoef(D, i, p, e) > 0 ? -sum : sum;
 }
 
-// deviation of population (i,p) stored at cell cs with cell scale s
+// deviation of population (i,p) of one cell with cell scale s
+template <int D, bool GH, class Get>
+__device__ __forceinline__ float dev_value_of(const Get& get, int i, int p, float s, float wc0)
+{
+    constexpr int Q = Lat<D>::Q;
+    if (!GH) return (i == 0 ? s * wc0 : 0.5f * s) * dev_code_of<D, false>(get, i, p);
+    if (i != 0) return 0.5f * s * dev_code_of<D, true>(get, i, p);
+    float sum = 0.f;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) sum += dev_code_of<D, true>(get, j, p);
+    return -0.5f * s * sum;
+}
+
+// the same, reading the codes of cell cs from the deviation arrays
 template <int D, typename H, bool GH>
 __device__ __forceinline__ float dev_value(const H* Dv, int64_t n, int i, int p, int cs, float s, float wc0)
 {
-    constexpr int Q = Lat<D>::Q;
-    if (!GH) return (i == 0 ? s * wc0 : 0.5f * s) * dev_code<D, H, false>(Dv, n, i, p, cs);
-    if (i != 0) return 0.5f * s * dev_code<D, H, true>(Dv, n, i, p, cs);
-    float sum = 0.f;
-#pragma unroll
-    for (int j = 1; j < Q; ++j) sum += dev_code<D, H, true>(Dv, n, j, p, cs);
-    return -0.5f * s * sum;
+    auto get = [&](int sl) { return h2f<H>(Dv[(int64_t)sl * n + cs]); };
+    return dev_value_of<D, GH>(get, i, p, s, wc0);
 }
 
 // Reconstruct population (i,p) stored at cell cs (moments M, deviations Dv).
@@ -977,12 +986,13 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
 // is.  The new moments are therefore (Lambda - Sp, Bbar), and the deviation of
 // the new state from their equilibrium is (1 - omega)(g - g0(m)) exactly.
 // Only that product is rounded; the post-collision populations are never
-// formed and their moments never summed again.
+// formed and their moments never summed again.  M receives the stored FP32
+// moments, code the stored 16-bit codes (slot order).
 template <int D, typename H, bool GH>
-__device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
-                                                  const float (&Sp)[Lat<D>::P], bool any_src, float omega,
-                                                  bool tau_half, const float (&rho)[Lat<D>::P],
-                                                  const float (&K)[D], int64_t n, int c, float* Mout, H* Dout)
+__device__ __forceinline__ void dev_encode(const float (&f)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
+                                           const float (&Sp)[Lat<D>::P], bool any_src, float omega, bool tau_half,
+                                           const float (&rho)[Lat<D>::P], const float (&K)[D],
+                                           float (&M)[Lat<D>::P + D], H (&code)[DevSlots<D, GH>::N])
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     float Lam[P], Bb[D];
@@ -994,12 +1004,12 @@ __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][La
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const float l2 = any_src ? Lam[p] - Sp[p] : Lam[p];
-        Mout[(int64_t)p * n + c] = l2;
+        M[p] = l2;
         m = fmaxf(m, fabsf(l2));
     }
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-        Mout[(int64_t)(P + b) * n + c] = Bb[b];
+        M[P + b] = Bb[b];
         m = fmaxf(m, fabsf(Bb[b]));
     }
     float s, inv;
@@ -1012,11 +1022,27 @@ __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][La
         for (int p = 0; p < P; ++p) {
             const int sl = dev_slot<D, GH>(i, p);
             if (sl < 0) continue;
-            float code;
-            if (i == 0) code = (f[0][p] - (rho[p] - float(D) * Lam[p])) * (f1 * (inv / wc0));
-            else code = (f[i][p] - 0.5f * twice_eq_moving<D, float>(i, p, Lam[p], Bb)) * km;
-            Dout[(int64_t)sl * n + c] = f2h<H>(sat16<H>(code));
+            float c;
+            if (i == 0) c = (f[0][p] - (rho[p] - float(D) * Lam[p])) * (f1 * (inv / wc0));
+            else c = (f[i][p] - 0.5f * twice_eq_moving<D, float>(i, p, Lam[p], Bb)) * km;
+            code[sl] = f2h<H>(sat16<H>(c));
         }
+}
+
+template <int D, typename H, bool GH>
+__device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
+                                                  const float (&Sp)[Lat<D>::P], bool any_src, float omega,
+                                                  bool tau_half, const float (&rho)[Lat<D>::P],
+                                                  const float (&K)[D], int64_t n, int c, float* Mout, H* Dout)
+{
+    constexpr int P = Lat<D>::P;
+    float M[P + D];
+    H code[DevSlots<D, GH>::N];
+    dev_encode<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half, rho, K, M, code);
+#pragma unroll
+    for (int q = 0; q < P + D; ++q) Mout[(int64_t)q * n + c] = M[q];
+#pragma unroll
+    for (int sl = 0; sl < DevSlots<D, GH>::N; ++sl) Dout[(int64_t)sl * n + c] = code[sl];
 }
 
 template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
@@ -1235,6 +1261,295 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
                                         Dout);
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D deviation storage, two steps per launch (temporal blocking)
+// ---------------------------------------------------------------------------
+// The column tiling, z-march and LDS buffers of k_step_fused3d, on the 16-bit
+// formats.  Step 1 runs on the tile grown by one cell (the frame) of plane zz:
+// it decodes the pulled populations from the stored state exactly as a single
+// step does (the pair moments and scale of the source cells come from an LDS
+// window of plane zz and from registers for planes zz -+ 1), collides, and
+// encodes the result as a single step would store it (dev_encode).  Instead of
+// writing that encoding it decodes it at once, as every reader of it would,
+// and hands the decoded populations to step 2 through LDS; step 2 on plane
+// zz-1 of the tile collides and stores.  Two launches of the single-step
+// kernel and one of this one therefore give the same bits.
+template <typename H, bool GH, bool MU>
+__global__ __launch_bounds__(NT) void k_step_dev3f(const float* Min, const H* Din, float* Mout, H* Dout,
+                                                  const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                                  const Geo g, const int lz, const FusedSrc<float> fs,
+                                                  const AmpPack<float, 2> amps, const float omega,
+                                                  const int tau_half)
+{
+    constexpr int D = 3, Q = 7, P = 3, NM = P + D, NSL = DevSlots<D, GH>::N;
+    constexpr int TX = 64, TY = 4;
+    constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;  // frame = tile + 1
+    constexpr int WW = TX + 4, WH = TY + 4, WC = WW * WH;              // window = frame + 1
+    constexpr int NRING = 2 * (WW - 2) + 2 * (WH - 2);                 // window minus frame and corners
+    static_assert(TC == NT && NRING <= NT, "tile and window ring");
+    constexpr int NIP = 5;                       // in-plane velocities 0, +x, +y, -x, -y
+    constexpr int CF = (FC + NT - 1) / NT;       // frame cells per thread
+    __shared__ float lin[NIP * P][FC];           // decoded in-plane outputs of plane zz-1 (frame)
+    __shared__ float lpz[3][P][TC];
+    __shared__ float lmz[P][TC];
+    __shared__ float lsrc[2][P][FC];
+    __shared__ float lw[NM][WC];                 // stored moments of plane zz over the window
+    __shared__ float lws[WC];                    // and their per-cell scale
+
+    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tx = b % g.tiles_x, r = b / g.tiles_x;
+    const int ty = r % g.tiles_y, zc = r / g.tiles_y;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = zc * lz;
+    const int z1 = min(z0 + lz, g.nz);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int hc = (ly + 1) * W + (lx + 1);
+    const int nxy = g.nx * g.ny;
+
+    int s0 = 0, s1 = 0;
+    if (fs.off) {
+        s0 = fs.off[b];
+        s1 = fs.off[b + 1];
+    }
+    const bool has_src = s1 > s0;
+
+    auto wrapx = [&](int v) { v %= g.nx; return v < 0 ? v + g.nx : v; };
+    auto wrapy = [&](int v) { v %= g.ny; return v < 0 ? v + g.ny : v; };
+
+    // this thread's frame cells (in-plane offset, window index) and ring cell
+    int f2d[CF], fwin[CF];
+    bool fact[CF];
+#pragma unroll
+    for (int j = 0; j < CF; ++j) {
+        const int k = threadIdx.x + j * NT;
+        const int hx = k % W, hy = k / W;
+        fact[j] = k < FC;
+        f2d[j] = wrapx(x0 - 1 + hx) + g.nx * wrapy(y0 - 1 + hy);
+        fwin[j] = (hy + 1) * WW + (hx + 1);
+    }
+    int r2d = 0, rwin = 0;
+    const bool ract = threadIdx.x < NRING;
+    {
+        const int k = threadIdx.x;
+        int wx, wy;
+        if (k < WW - 2) { wx = 1 + k; wy = 0; }
+        else if (k < 2 * (WW - 2)) { wx = 1 + k - (WW - 2); wy = WH - 1; }
+        else if (k < 2 * (WW - 2) + (WH - 2)) { wx = 0; wy = 1 + k - 2 * (WW - 2); }
+        else { wx = WW - 1; wy = 1 + k - 2 * (WW - 2) - (WH - 2); }
+        r2d = wrapx(x0 - 2 + wx) + g.nx * wrapy(y0 - 2 + wy);
+        rwin = wy * WW + wx;
+    }
+
+    // stored moments of the frame cells for planes zz-1, zz, zz+1
+    float mp[CF][NM], mc[CF][NM], mn[CF][NM];
+    auto load_m = [&](int zz, float (&dst)[CF][NM]) {
+        int gz = zz % g.nz;
+        if (gz < 0) gz += g.nz;
+        const int64_t zoff = (int64_t)gz * nxy;
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            if (!fact[j]) continue;
+#pragma unroll
+            for (int t = 0; t < NM; ++t) dst[j][t] = Min[(int64_t)t * g.n + zoff + f2d[j]];
+        }
+    };
+    auto scale_of = [](const float (&m)[NM]) {
+        float mx = 0.f;
+#pragma unroll
+        for (int t = 0; t < NM; ++t) mx = fmaxf(mx, fabsf(m[t]));
+        float sv, iv;
+        pow2_scale(mx, sv, iv);
+        return sv;
+    };
+    // decoded population (i,p) from stored moments mm and scale sc of its
+    // source cell cs, for a reader with rest weight wc0 (as k_step_dev3z)
+    auto pulled = [&](const float (&mm)[NM], float sc, int i, int p, int64_t cs, float wc0) {
+        float Lam[P], Bb[D];
+#pragma unroll
+        for (int t = 0; t < P; ++t) Lam[t] = (t == p) ? mm[t] : 0.f;
+        const int a = pair_a(D, p), bq = pair_b(D, p);
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            const bool need = i != 0 && ((e == bq && cvel(D, i, a) != 0) || (e == a && cvel(D, i, bq) != 0));
+            Bb[e] = need ? mm[P + e] : 0.f;
+        }
+        const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0);
+        return g0 + dev_value<D, H, GH>(Din, g.n, i, p, (int)cs, sc, wc0);
+    };
+
+    load_m(z0 - 2, mp);
+    load_m(z0 - 1, mc);
+    load_m(z0, mn);
+    for (int zz = z0 - 1; zz <= z1; ++zz) {
+        const int rel = zz - (z0 - 1);
+        const int bi = rel & 1;
+        int gz = zz % g.nz;
+        if (gz < 0) gz += g.nz;
+        const int64_t zoff = (int64_t)gz * nxy;
+        if (has_src) {
+            for (int k = threadIdx.x; k < P * FC; k += NT) (&lsrc[bi][0][0])[k] = 0.f;
+            __syncthreads();
+            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+                const int2 e = fs.ent[k];
+                if (e.x / FC == rel) lsrc[bi][e.y][e.x % FC] = fs.val[k];
+            }
+        }
+        // moments window of plane zz: the frame from registers, the ring from HBM
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            if (!fact[j]) continue;
+#pragma unroll
+            for (int t = 0; t < NM; ++t) lw[t][fwin[j]] = mc[j][t];
+            lws[fwin[j]] = scale_of(mc[j]);
+        }
+        if (ract) {
+            float rm[NM];
+#pragma unroll
+            for (int t = 0; t < NM; ++t) {
+                rm[t] = Min[(int64_t)t * g.n + zoff + r2d];
+                lw[t][rwin] = rm[t];
+            }
+            lws[rwin] = scale_of(rm);
+        }
+        __syncthreads();
+        // ---- step 1 on the frame cells of plane zz
+        float held[CF][NIP * P];
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            if (!fact[j]) continue;
+            const int k = threadIdx.x + j * NT;
+            const int hx = k % W, hy = k / W;
+            const int64_t c = zoff + f2d[j];
+            const int gx = f2d[j] % g.nx, gy = f2d[j] / g.nx;
+            const float cl2 = cl2a[c];
+            const float wc0 = 1.f / cl2 - float(D);
+            float f[Q][P];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int cx = cvel(D, i, 0), cy = cvel(D, i, 1), cz = cvel(D, i, 2);
+                int64_t cs;
+                float sc;
+                float mm[NM];
+                if (cz == 0) {
+                    const int wi = fwin[j] - cx - cy * WW;
+#pragma unroll
+                    for (int t = 0; t < NM; ++t) mm[t] = lw[t][wi];
+                    sc = lws[wi];
+                    cs = zoff + wrapx(gx - cx) + (int64_t)g.nx * wrapy(gy - cy);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NM; ++t) mm[t] = cz > 0 ? mp[j][t] : mn[j][t];
+                    sc = scale_of(mm);
+                    int sz = (gz - cz) % g.nz;
+                    if (sz < 0) sz += g.nz;
+                    cs = (int64_t)sz * nxy + f2d[j];
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) f[i][p] = pulled(mm, sc, i, p, cs, wc0);
+            }
+            float rho[P], K[D], Sp[P];
+            moments<D, float>(f, rho, K);
+#pragma unroll
+            for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[bi][p][k] * amps.a[0] : 0.f;
+            if (MU) {
+                float dl[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + c];
+                add_mu_source<D, float>(K, cl2, dl, Sp);
+            }
+            float M1[NM];
+            H cd[NSL];
+            dev_encode<D, H, GH>(f, cl2, wc0, Sp, has_src || MU, omega, tau_half != 0, rho, K, M1, cd);
+            // decode the encoding as its readers will
+            const float s1c = scale_of(M1);
+            auto get = [&](int sl) { return h2f<H>(cd[sl]); };
+            float out[Q][P];
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    float Lam[P], Bb[D];
+#pragma unroll
+                    for (int t = 0; t < P; ++t) Lam[t] = (t == p) ? M1[t] : 0.f;
+                    const int a = pair_a(D, p), bq = pair_b(D, p);
+#pragma unroll
+                    for (int e = 0; e < D; ++e) {
+                        const bool need = i != 0 && ((e == bq && cvel(D, i, a) != 0) || (e == a && cvel(D, i, bq) != 0));
+                        Bb[e] = need ? M1[P + e] : 0.f;
+                    }
+                    out[i][p] = dev_eq<D>(i, p, Lam, Bb, wc0) + dev_value_of<D, GH>(get, i, p, s1c, wc0);
+                }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int sl = i == 0 ? 0 : (i == 1 ? 1 : (i == 2 ? 2 : (i == 4 ? 3 : (i == 5 ? 4 : -1))));
+                if (sl >= 0) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) held[j][sl * P + p] = out[i][p];
+                }
+            }
+            const bool tile = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY;
+            if (tile) {
+                const int tcell = (hy - 1) * TX + (hx - 1);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    lpz[rel % 3][p][tcell] = out[3][p];
+                    lmz[p][tcell] = out[6][p];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- step 2 on plane zz-1 of the tile
+        const int zc2 = zz - 1;
+        if (zc2 >= z0 && zc2 < z1) {
+            const int x = x0 + lx, y = y0 + ly;
+            if (x < g.nx && y < g.ny) {
+                const int pb = (rel - 1) & 1;
+                float f[Q][P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    f[0][p] = lin[0 * P + p][hc];
+                    f[1][p] = lin[1 * P + p][hc - 1];
+                    f[2][p] = lin[2 * P + p][hc - W];
+                    f[4][p] = lin[3 * P + p][hc + 1];
+                    f[5][p] = lin[4 * P + p][hc + W];
+                    f[3][p] = lpz[(rel + 1) % 3][p][threadIdx.x];
+                    f[6][p] = lmz[p][threadIdx.x];
+                }
+                const int c = x + g.nx * (y + g.ny * zc2);
+                const float cl2 = cl2a[c];
+                const float wc0 = 1.f / cl2 - float(D);
+                float rho[P], K[D], Sp[P];
+                moments<D, float>(f, rho, K);
+#pragma unroll
+                for (int p = 0; p < P; ++p) Sp[p] = has_src ? lsrc[pb][p][hc] * amps.a[1] : 0.f;
+                if (MU) {
+                    float dl[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + c];
+                    add_mu_source<D, float>(K, cl2, dl, Sp);
+                }
+                dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, has_src || MU, omega, tau_half != 0, rho, K, g.n, c,
+                                            Mout, Dout);
+            }
+        }
+        __syncthreads();
+        // plane zz's decoded in-plane outputs into the frame buffer; roll the
+        // moment registers one plane on
+#pragma unroll
+        for (int j = 0; j < CF; ++j) {
+            if (!fact[j]) continue;
+            const int k = threadIdx.x + j * NT;
+#pragma unroll
+            for (int q = 0; q < NIP * P; ++q) lin[q][k] = held[j][q];
+#pragma unroll
+            for (int t = 0; t < NM; ++t) {
+                mp[j][t] = mc[j][t];
+                mc[j][t] = mn[j][t];
+            }
+        }
+        if (zz < z1) load_m(zz + 2, mn);
     }
 }
 

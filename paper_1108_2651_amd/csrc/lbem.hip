@@ -296,9 +296,13 @@ static hipError_t go_fused3(lbem_s* h, const T* src, T* dst, const double* amp)
     return go_fused3_t<T, 32, 8, false>(h, src, dst, amp);
 }
 
+// formats with a multi-step kernel: the plain FP32/FP64 ones, and the 3D
+// deviation formats (two steps)
+static bool fused_format(const lbem_s* h) { return h->prec <= LBEM_F32 || (is_dev(h->prec) && h->D == 3); }
+
 static bool fused_ok(const lbem_s* h)
 {
-    return h->prec <= LBEM_F32 && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1 && !has_bx(h);
+    return fused_format(h) && h->streaming == LBEM_STREAM_PULL && h->fuse_ns > 1 && !has_bx(h);
 }
 
 // plain formats: populations stored as S, arithmetic in T
@@ -454,6 +458,32 @@ struct DevImpl : Impl {
         h->layout = LAYOUT_PULL_PENDING;
         return e;
     }
+    hipError_t step_fused(lbem_s* h, const double* amp) override
+    {
+        if constexpr (D == 3) {
+            FusedSrc<float> fs;
+            fs.off = h->nfsrc ? h->fsrc_off : nullptr;
+            fs.ent = h->fsrc_ent;
+            fs.val = (const float*)h->fsrc_val;
+            AmpPack<float, 2> a;
+            for (int j = 0; j < 2; ++j) a.a[j] = (float)(amp ? amp[j] : 0.0);
+            const int from = h->cur, to = 1 - h->cur;
+            if (h->mu_set)
+                hipLaunchKernelGGL((k_step_dev3f<H, GH, true>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream,
+                                   M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                                   (const float*)h->dlnmu, h->fgeo, h->f3_lz, fs, a, (float)(1.0 / h->cfg.tau),
+                                   (int)(h->cfg.tau == 0.5));
+            else
+                hipLaunchKernelGGL((k_step_dev3f<H, GH, false>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream,
+                                   M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                                   (const float*)h->dlnmu, h->fgeo, h->f3_lz, fs, a, (float)(1.0 / h->cfg.tau),
+                                   (int)(h->cfg.tau == 0.5));
+            h->cur = to;
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     hipError_t fields(lbem_s* h, double* E, double* B, double* partials) override
     {
         if (h->layout == LAYOUT_NATURAL)
@@ -532,6 +562,11 @@ static void make_fused3_geo(lbem_s* h)
     const bool small = (double)h->n < SMALL3D;
     h->fuse_ns = env_int("LBEM_FUSE3", (f64 || small) ? 1 : 2) == 2 ? 2 : 1;
     h->f3_tx = env_int("LBEM_FUSE3_TX", f64 ? 32 : 64) == 64 && !f64 ? 64 : 32;
+    if (is_dev(h->prec)) {
+        // the two-step deviation kernel (64 x 4 column tiles)
+        h->fuse_ns = env_int("LBEM_DEV3F", 0) ? 2 : 1;
+        h->f3_tx = 64;
+    }
     h->f3_ty = NT / h->f3_tx;
     Geo& g = h->fgeo;
     g = h->geo;
@@ -1149,7 +1184,7 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
         const int rc = build_zmarch_source(h, cv, pp);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
-    if (h->prec <= LBEM_F32 && h->fuse_ns > 1) {
+    if (fused_format(h) && h->fuse_ns > 1) {
         std::vector<double> dense((size_t)n, 0.0);
         for (size_t k = 0; k < merged.size(); ++k) dense[(size_t)merged[k].first] = src_value[k];
         const int rc = D == 2 ? build_fused_source(h, dense) : build_fused3_source(h, dense, pp);

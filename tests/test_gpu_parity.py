@@ -116,6 +116,25 @@ def test_temporal_blocking_3d_bitwise(prec, shape, mu):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
 
 
+@pytest.mark.parametrize("mu", [False, True])
+@pytest.mark.parametrize("shape", [(40, 24, 20), (70, 9, 5), (33, 17, 37), (5, 3, 7), (128, 4, 2)])
+def test_deviation_two_step_kernel_bitwise(shape, mu):
+    """The two-step 3D deviation kernel (decode, collide, encode and decode
+    again in registers between the steps) equals two single steps bit for bit:
+    every 16-bit format, sources with periodic images, mu term, ragged boxes,
+    several chunk lengths and block orders."""
+    p = random_problem(3, shape, seed=sum(shape) + 17, mu=mu, nsteps=31)
+    for prec in LOWP:
+        ref = gpu_run(p, 31, prec, "pull", env={"LBEM_DEV3F": 0}).moments()
+        for env in (dict(LBEM_FUSE3_LZ=32), dict(LBEM_FUSE3_LZ=3, LBEM_FUSE3_XCD=1), dict(LBEM_FUSE3_LZ=1)):
+            env["LBEM_DEV3F"] = 1
+            announce(f"dev two-step {prec} {shape} mu={mu} {env}")
+            s = gpu_run(p, 31, prec, "pull", env=env)
+            assert s.steps_per_launch == 2, env
+            got = s.moments()
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (prec, env)
+
+
 def test_tau_not_half():
     p = random_problem(2, (40, 24, 1), seed=3, nsteps=80)
     compare(p, 80, "f64", tau=0.8)
