@@ -163,8 +163,10 @@ int lbem_energy(lbem_t h, double out[4]);
 int64_t lbem_time(lbem_t h);
 
 /* Time steps advanced per kernel launch by lbem_step on this handle (1, or 2-4
- * when the plain formats fuse several steps into one pass through LDS; the
- * result is identical to single steps).  EINVAL for NULL. */
+ * when several steps are fused into one pass through LDS: the plain formats by
+ * default, the 3D 16-bit formats two steps when the environment variable
+ * LBEM_DEV3F=1 is set at creation; the result is identical to single steps).
+ * EINVAL for NULL. */
 int lbem_steps_per_launch(lbem_t h);
 
 /* ---- exact checkpoint / resume ----
