@@ -259,11 +259,12 @@ def size_sweep(steps: int = 100, warmup: int = 5) -> list:
     """Roofline sweep across the Infinity-Cache boundary: 3D spheres medium
     from 64^3 to 512^3 in FP32 (pull, fused pair; AA single steps), plain
     FP16 storage (AA single steps) and the two 16-bit deviation formats; 2D
-    from 512^2 to 8192^2 in FP32."""
+    from 512^2 to 8192^2 in FP32 (fused and AA) and the two deviation formats."""
     rows = []
     plan = [(f"3d{n}", prec, st) for n in (64, 96, 128, 160, 192, 256, 320, 384, 448, 512)
             for prec, st in (("f32", "pull"), ("f32", "aa"), ("f16", "aa"), ("f16dev", "pull"), ("f16ghost", "pull"))]
-    plan += [(f"2d{n}", "f32", st) for n in (512, 1024, 2048, 4096, 8192) for st in ("pull", "aa")]
+    plan += [(f"2d{n}", prec, st) for n in (512, 1024, 2048, 4096, 8192)
+             for prec, st in (("f32", "pull"), ("f32", "aa"), ("f16dev", "pull"), ("f16ghost", "pull"))]
     for name, prec, st in plan:
         n = int(name[2:])
         k = max(20, min(steps * 8, int(steps * (256 ** 3 if name.startswith("3d") else 2048 ** 2) /

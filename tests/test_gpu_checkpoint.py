@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [(2, (70, 33, 1), "f64", "pull"), (2, (96, 40, 1), "f32", "pull"), (2, (64, 48, 1), "f32", "aa"),
          (2, (50, 31, 1), "f16ghost", "pull"), (3, (24, 20, 18), "f32", "aa"), (3, (24, 20, 18), "f32", "pull"),
-         (3, (19, 13, 11), "f64", "aa"), (3, (20, 16, 12), "bf16dev", "pull"), (3, (20, 16, 12), "f16ghost", "pull")]
+         (3, (19, 13, 11), "f64", "aa"), (3, (20, 16, 12), "bf16dev", "pull"), (3, (20, 16, 12), "f16ghost", "pull"),
+         (3, (22, 14, 10), "f16", "aa"), (2, (40, 30, 1), "f16", "pull")]
 
 
 def make(p, prec, streaming):

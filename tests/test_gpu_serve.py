@@ -87,6 +87,11 @@ def test_batch_rejects_unsupported_members():
     with pytest.raises(lbem.LbemError) as e:
         b.run([s4], [1])                        # no batched ghost-coordinate kernels
     assert e.value.code == lbem.LBEM_EINVAL
+    s5 = lbem.Solver(2, q.shape, "f16", streaming="aa", stream=st)
+    s5.setup(q)
+    with pytest.raises(lbem.LbemError) as e:
+        b.run([s5], [1])                        # nor plain FP16 ones
+    assert e.value.code == lbem.LBEM_EINVAL
     b.close()
 
 
