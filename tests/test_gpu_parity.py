@@ -142,6 +142,20 @@ def test_tau_not_half():
     compare(p3, 40, "f64", tau=1.3)
 
 
+@pytest.mark.parametrize("prec", ["f32"] + LOWP)
+def test_tau_not_half_every_format(prec):
+    """Away from tau = 1/2 the collision relaxes instead of reflecting: the
+    16-bit formats then store (1 - 1/tau)(g - g0) as the deviation.  Every
+    format against the oracle with sources and mu, in 2D and 3D, through the
+    gather, z-marching and multi-step kernels."""
+    p = random_problem(2, (40, 24, 1), seed=33, mu=True, nsteps=80)
+    compare(p, 80, prec, "pull", tau=0.8)
+    p3 = random_problem(3, (20, 12, 10), seed=34, mu=True, nsteps=40)
+    envs = [None, {"LBEM_FUSE3": 2}] if prec == "f32" else [None, {"LBEM_DEV3Z": 1}, {"LBEM_DEV3F": 1}]
+    for env in envs:
+        compare(p3, 40, prec, "pull", tau=1.3, env=env)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
 def test_diagnostics_match_oracle(dim, streaming):
