@@ -4,8 +4,9 @@ the 16-bit accuracy bar.
 
 * Structure, bit for bit: initialising and then every single step of the FP16
   handle equals the FP32 handle run on the decoded FP16 state, rounded to
-  FP16 (round to nearest even) -- with mu, walls, absorber, the source, pull
-  and AA streaming.  The FP32 path itself is held to the oracle elsewhere.
+  FP16 (round to nearest even) -- with mu, walls, absorber, a dispersion
+  pole, the source, pull and AA streaming.  The FP32 path itself is held to
+  the oracle elsewhere.
 * Against the oracle: each store perturbs every population by at most the
   FP16 unit roundoff u = 2^-11 relative; at tau = 1/2 the collision reflects
   about the equilibrium, so the step is an isometry in the 1/w-weighted norm
@@ -27,9 +28,10 @@ pytestmark = pytest.mark.gpu
 HDR = 128
 U16 = 2.0 ** -11
 
-CASES = [(2, (70, 33, 1), "pull", False, [], False), (2, (64, 48, 1), "aa", True, [], False),
-         (3, (19, 13, 11), "pull", True, [(1, "pec")], True), (3, (16, 12, 10), "aa", False, [], False),
-         (3, (20, 9, 14), "pull", False, [(0, "pmc"), (2, "pec")], False)]
+CASES = [(2, (70, 33, 1), "pull", False, [], False, False), (2, (64, 48, 1), "aa", True, [], False, False),
+         (3, (19, 13, 11), "pull", True, [(1, "pec")], True, False), (3, (16, 12, 10), "aa", False, [], False, False),
+         (3, (20, 9, 14), "pull", False, [(0, "pmc"), (2, "pec")], False, False),
+         (2, (50, 36, 1), "pull", False, [], False, True), (3, (18, 14, 12), "pull", True, [(2, "pmc")], True, True)]
 
 
 def populations(s, dtype, m):
@@ -37,8 +39,15 @@ def populations(s, dtype, m):
     return blob, blob[HDR:HDR + m * np.dtype(dtype).itemsize].view(dtype).copy()
 
 
-@pytest.mark.parametrize("dim,shape,st,mu,walls,absorber", CASES)
-def test_f16_steps_are_rounded_fp32_steps(dim, shape, st, mu, walls, absorber):
+def aux_region(blob):
+    """Byte range of the dispersion auxiliaries (payload and aux sizes are the
+    header's int64 fields at offsets 56 and 64)."""
+    pay, aux = (int(v) for v in blob[56:72].view(np.int64))
+    return slice(HDR + pay, HDR + pay + aux)
+
+
+@pytest.mark.parametrize("dim,shape,st,mu,walls,absorber,disp", CASES)
+def test_f16_steps_are_rounded_fp32_steps(dim, shape, st, mu, walls, absorber, disp):
     p = random_problem(dim, shape, seed=sum(shape) + 11, mu=mu, nsteps=8)
     Q, P = 2 * dim + 1, dim * (dim - 1) // 2
     m = Q * P * p.n
@@ -51,6 +60,8 @@ def test_f16_steps_are_rounded_fp32_steps(dim, shape, st, mu, walls, absorber):
         x.set_medium(p.eps_r, p.mu_r)
         if sigma is not None:
             x.set_absorber(sigma)
+        if disp:
+            x.set_dispersion(np.linspace(0.0, 0.02, p.n), 0.01, 0.05)
         x.init_fields(p.E0, p.B0)
         x.set_source(p.src_comp, p.src_cells, p.src_weights)
     _, a16 = populations(h, np.float16, m)
@@ -59,6 +70,9 @@ def test_f16_steps_are_rounded_fp32_steps(dim, shape, st, mu, walls, absorber):
     for k in range(6):
         blob, _ = populations(f, np.float32, m)
         blob[HDR:HDR + 4 * m] = a16.astype(np.float32).view(np.uint8)
+        if disp:   # the auxiliary P, J follow the FP16 handle's fields too
+            b16 = h.get_state()
+            blob[aux_region(blob)] = b16[aux_region(b16)]
         f.set_state(blob)
         h.step(1, p.amp[k:k + 1])
         f.step(1, p.amp[k:k + 1])
@@ -66,7 +80,7 @@ def test_f16_steps_are_rounded_fp32_steps(dim, shape, st, mu, walls, absorber):
         _, a32 = populations(f, np.float32, m)
         diff = np.count_nonzero(a16.view(np.uint16) != a32.astype(np.float16).view(np.uint16))
         assert diff == 0, (k, diff)
-    announce(f"f16 plain {dim}D {shape} {st} mu={mu} walls={walls}: 6 steps bitwise = rounded FP32 steps")
+    announce(f"f16 plain {dim}D {shape} {st} mu={mu} walls={walls} disp={disp}: 6 steps bitwise = rounded FP32 steps")
     for x in (h, f):
         x.close()
 
