@@ -474,6 +474,20 @@ __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T
 // bit.  Periodic wrap is applied to the frame's global coordinates.
 constexpr int TXF = 64;
 
+// Element idx of an array whose byte size fits 32 bits: the offset is formed
+// in 32-bit arithmetic, so the load or store takes the scalar-base plus
+// 32-bit vector-offset form and needs no 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, unsigned idx)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* base, unsigned idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 template <typename T>
 struct FusedSrc {
     const int* off;      // per tile range into ent/val (nullptr: no source)
@@ -486,7 +500,8 @@ struct AmpPack {
     T a[NS];             // source amplitude of each fused step
 };
 
-template <typename T, int NS, int TY, bool MU>
+// O32: every population plane fits 2^32 bytes (32-bit element offsets)
+template <typename T, int NS, int TY, bool MU, bool O32>
 __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g,
                                                     const FusedSrc<T> fs, const AmpPack<T, NS> amps,
@@ -530,21 +545,42 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         T fv0[C0][Q][1];
         T cl0[C0];
         T dl0[C0][2];
+        // frame coordinates wrap at most once when the box is at least a
+        // frame wide (no division); smaller boxes take the remainder
+        const bool wide = g.nx >= W && g.ny >= FH;
 #pragma unroll
         for (int j = 0; j < C0; ++j) {
             const int k = threadIdx.x + j * NT;
             if (k < FC) {
                 const int fx = k % W, fy = k / W;
-                int gx = (x0 + fx) % g.nx, gy = (y0 + fy) % g.ny;
-                if (gx < 0) gx += g.nx;
-                if (gy < 0) gy += g.ny;
+                int gx = x0 + fx, gy = y0 + fy;
+                if (wide) {
+                    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+                    gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+                } else {
+                    gx %= g.nx;
+                    gy %= g.ny;
+                    if (gx < 0) gx += g.nx;
+                    if (gy < 0) gy += g.ny;
+                }
                 const Cell C = make_cell(g, gx, gy, 0);
+                if constexpr (O32) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) fv0[j][i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
-                cl0[j] = cl2a[C.c];
-                if (MU) {
-                    dl0[j][0] = dlnmu[C.c];
-                    dl0[j][1] = dlnmu[(int64_t)g.n + C.c];
+                    for (int i = 0; i < Q; ++i)
+                        fv0[j][i][0] = at32(src + (int64_t)i * g.n, (unsigned)read_cell<2, R_PULL>(C, i));
+                    cl0[j] = at32(cl2a, (unsigned)C.c);
+                    if (MU) {
+                        dl0[j][0] = at32(dlnmu, (unsigned)C.c);
+                        dl0[j][1] = at32(dlnmu + g.n, (unsigned)C.c);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) fv0[j][i][0] = src[(int64_t)i * g.n + read_cell<2, R_PULL>(C, i)];
+                    cl0[j] = cl2a[C.c];
+                    if (MU) {
+                        dl0[j][0] = dlnmu[C.c];
+                        dl0[j][1] = dlnmu[(int64_t)g.n + C.c];
+                    }
                 }
             }
         }
@@ -602,7 +638,10 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
                 if (gx < g.nx && gy < g.ny) {
                     const int gcell = gx + g.nx * gy;
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.n + gcell] = o[i][0];
+                    for (int i = 0; i < Q; ++i) {
+                        if constexpr (O32) at32(dst + (int64_t)i * g.n, (unsigned)gcell) = o[i][0];
+                        else dst[(int64_t)i * g.n + gcell] = o[i][0];
+                    }
                 }
             } else {
 #pragma unroll

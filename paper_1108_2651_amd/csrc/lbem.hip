@@ -238,9 +238,15 @@ static hipError_t go_fused_ntm(lbem_s* h, const T* src, T* dst, const double* am
     fs.val = (const T*)h->fsrc_val;
     AmpPack<T, NS> a;
     for (int j = 0; j < NS; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
-    hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream, src,
-                       dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau),
-                       (int)(h->cfg.tau == 0.5));
+    // 32-bit element offsets while one population plane fits 2^32 bytes
+    if ((uint64_t)h->n * sizeof(T) <= (1ull << 32))
+        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, true>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream,
+                           src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau),
+                           (int)(h->cfg.tau == 0.5));
+    else
+        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, false>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream,
+                           src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau),
+                           (int)(h->cfg.tau == 0.5));
     return hipGetLastError();
 }
 
