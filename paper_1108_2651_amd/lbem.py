@@ -118,8 +118,11 @@ def required_bytes(dim, shape, prec="f32", **kw) -> int:
 class Solver:
     """One lattice-BGK Maxwell solve on the current CUDA/HIP device.
 
-    The device arena is a torch uint8 tensor; launches go to torch's current
-    stream (or ``stream``, a torch.cuda.Stream)."""
+    ``prec`` names the storage format (a key of PREC: "f64", "f32", the 16-bit
+    deviation formats "f16dev"/"bf16dev", the ghost-coordinate formats
+    "f16ghost"/"bf16ghost", or plain "f16"); ``streaming`` is "auto", "pull" or
+    "aa".  The device arena is a torch uint8 tensor; launches go to torch's
+    current stream (or ``stream``, a torch.cuda.Stream)."""
 
     def __init__(self, dim, shape, prec="f32", tau=0.5, w0_vac=1.0 / 3.0, streaming="auto",
                  mu_varies=False, stream=None):
