@@ -62,6 +62,27 @@ def test_config2_full_grid_1000_steps_fp32():
     assert eE <= 1e-5 and eB <= 1e-5, (eE, eB)
 
 
+def test_config2_recipe_5000_steps_fp32():
+    """The whole length of the 2D benchmark run (5000 steps, waves wrapping
+    through the periodic box many times) on the same recipe at 512^2, whole
+    grid against the oracle.  FP32 rounding errors add up at most linearly in
+    the number of steps, so the bar is the 1000-step one scaled by 5: 5e-5."""
+    from gpu_util import oracle_run, rel
+    k = 5000
+    p = inputs.config2(nsteps=k, n=512)
+    announce("config2 recipe 512^2 fp32 full grid, 5000 steps (oracle on all host cores)")
+    s = lbem.Solver(p.dim, p.shape, "f32", w0_vac=p.w0_vac)
+    s.setup(p)
+    assert s.steps_per_launch == 2
+    s.step(k, p.amp[:k])
+    Eg, Bg = s.moments()
+    s.close()
+    Eo, Bo = oracle_run(p, k).fields()
+    eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+    announce(f"  rel L2 E={eE:.3e} B={eB:.3e}")
+    assert eE <= 5e-5 and eB <= 5e-5, (eE, eB)
+
+
 def test_config2_full_2048_fp32_fused():
     """The benchmark's primary workload and launch configuration (2048^2
     FP32, two time steps per launch), 64 steps, 6 sampled cells including
