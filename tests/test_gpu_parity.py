@@ -135,6 +135,19 @@ def test_deviation_two_step_kernel_bitwise(shape, mu):
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (prec, env)
 
 
+@pytest.mark.parametrize("dim,shape,prec", [(2, (48, 40, 1), "f32"), (3, (20, 16, 12), "f64"),
+                                             (3, (20, 16, 12), "f16ghost")])
+def test_repeated_source_cells_add_up(dim, shape, prec):
+    """A source cell listed more than once carries the sum of its weights, in
+    the library as in the oracle (sparse, fused-frame and z-march tables)."""
+    p = random_problem(dim, shape, seed=sum(shape) + 41, nsteps=40)
+    rng = np.random.default_rng(5)
+    extra = rng.choice(p.src_cells, size=6, replace=False)
+    p.src_cells = np.concatenate([p.src_cells, extra, extra[:2]])
+    p.src_weights = np.concatenate([p.src_weights, rng.standard_normal(8)])
+    compare(p, 40, prec, "pull")
+
+
 def test_tau_not_half():
     p = random_problem(2, (40, 24, 1), seed=3, nsteps=80)
     compare(p, 80, "f64", tau=0.8)

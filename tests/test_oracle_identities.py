@@ -218,6 +218,26 @@ def test_uniform_current_follows_the_amplitude_series(dim, shape, comp):
         assert np.abs(B).max() < 1e-14
 
 
+def test_source_entries_add_up():
+    # the current density is the sum of the listed contributions: a cell
+    # listed twice carries the sum of its weights
+    shape = (9, 7, 1)
+    n = 63
+    rng = np.random.default_rng(12)
+    eps = rng.uniform(1.0, 3.0, n)
+    amp = rng.standard_normal(12)
+    out = []
+    for cells, weights in (([3, 3, 40], [0.5, 0.25, 1.0]), ([3, 40], [0.75, 1.0])):
+        o = O.Oracle(2, shape)
+        o.set_medium(eps)
+        o.init_fields(np.zeros((3, n)), np.zeros((3, n)))
+        o.set_source(2, np.array(cells), np.array(weights))
+        o.step(12, amp)
+        out.append(o.fields())
+    for a, b in zip(out[0], out[1]):
+        assert np.abs(a - b).max() <= 1e-15 * max(np.abs(b).max(), 1e-300)
+
+
 def test_medium_stability_bounds():
     o = O.Oracle(2, (4, 4, 1), 0.5, 1.0 / 3.0)
     # eps_r * mu_r < 1 - w0_vac gives w0 < 0: rejected

@@ -110,6 +110,20 @@ MUTANTS = [
      "for (int b = 0; b < D; ++b) Bbar[b] = Bp[b];"),
     ("Q_c without the c_L^2 factor", "qc += o->cL2[x] * q;", "qc += q;"),
     ("energy without eps_abs", "en += o->eps_abs[x] * e2 + b2 / o->mu_r[x];", "en += e2 + b2 / o->mu_r[x];"),
+    ("anisotropy: rest weight 1 - sum/2", "o->w0[x] = 1.0 - sum;", "o->w0[x] = 1.0 - 0.5 * sum;"),
+    ("anisotropy: weights of the next axis", "if (o->c[i][a] != 0) w[i] = o->wax[a * o->n + x];",
+     "if (o->c[i][a] != 0) w[i] = o->wax[((a + 1) % o->D) * o->n + x];"),
+    ("Bbar denominator without the factor 2", "if (a != b) rs += 2.0 * w[1 + a] / cl2;",
+     "if (a != b) rs += w[1 + a] / cl2;"),
+    ("dispersion: source from the old J", "Sp[gm] = -Jn;", "Sp[gm] = -Jo;"),
+    ("dispersion: damping denominator 1 + gamma", "wp2 * E[gm] - w02 * Po) / (1.0 + 0.5 * gam);",
+     "wp2 * E[gm] - w02 * Po) / (1.0 + gam);"),
+    ("wall test off by one at the low face", "(v[a] + o->c[i][a] < 0 || v[a] + o->c[i][a] >= nn[a])",
+     "(v[a] + o->c[i][a] <= 0 || v[a] + o->c[i][a] >= nn[a])"),
+    ("source footprint overwritten instead of summed", "o->jd[comp[k] * o->n + cell[k]] += weight[k];",
+     "o->jd[comp[k] * o->n + cell[k]] = weight[k];"),
+    ("initial fields: B used as K in 3D (no Bbar)", "double w[7], Bp[3] = {B[x], B[n + x], B[2 * n + x]};",
+     "double w[7], Bp[3] = {B[x] * (D - 1), B[n + x] * (D - 1), B[2 * n + x] * (D - 1)};"),
 ]
 
 
