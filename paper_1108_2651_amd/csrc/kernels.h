@@ -390,7 +390,43 @@ __device__ __forceinline__ S st_pop(T v) { return (S)v; }
 template <>
 __device__ __forceinline__ __half st_pop<__half, float>(float v) { return __float2half_rn(v); }
 
-template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX, typename S = T>
+// Global access with the streaming (non-temporal) cache policy when NTS is
+// set, plain access otherwise; the values are the same either way.  A 3D step
+// on a lattice larger than the last-level cache touches each stored value once
+// per launch, and marking those lines for early eviction keeps the caches for
+// the halo lines that neighbouring tiles share.  Loads that neighbouring tiles
+// share are never marked: those lose their reuse.
+template <bool NTS, typename S>
+__device__ __forceinline__ S ld_stream(const S* p)
+{
+    if constexpr (!NTS) {
+        return *p;
+    } else if constexpr (sizeof(S) == 2) {
+        const unsigned short u = __builtin_nontemporal_load((const unsigned short*)p);
+        S r;
+        __builtin_memcpy(&r, &u, 2);
+        return r;
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+}
+template <bool NTS, typename S>
+__device__ __forceinline__ void st_stream(S* p, S v)
+{
+    if constexpr (!NTS) {
+        *p = v;
+    } else if constexpr (sizeof(S) == 2) {
+        unsigned short u;
+        __builtin_memcpy(&u, &v, 2);
+        __builtin_nontemporal_store(u, (unsigned short*)p);
+    } else {
+        __builtin_nontemporal_store(v, p);
+    }
+}
+
+// NTS: streaming loads and stores of the populations (each is read and written
+// once per launch; large 3D lattices, no cell extras)
+template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX, typename S = T, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T* __restrict__ cl2a,
                                                   const T* __restrict__ dlnmu, const Geo g,
                                                   const SrcArgs<T> s, const T omega, const int tau_half,
@@ -416,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T
                     const T v = ld_pop<T>(src[(int64_t)(opp(D, i) * P + p) * g.n + C.c]);
                     f[i][p] = wall_negates<D>(bc, i, p) ? -v : v;
                 } else {
-                    f[i][p] = ld_pop<T>(src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]);
+                    f[i][p] = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]));
                 }
             }
         const T cl2 = cl2a[C.c];
@@ -457,7 +493,7 @@ __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T
         for (int i = 0; i < Q; ++i)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = st_pop<S>(out[i][p]);
+                st_stream<NTS>(&dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)], st_pop<S>(out[i][p]));
     }
 }
 
@@ -664,7 +700,8 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // only then stores plane zz's in-plane components into the single LDS frame
 // (one frame instead of two keeps three blocks per CU).  Every update is the
 // same collide() as the single-step kernel: bit-identical.
-template <typename T, int TX, int TY, bool MU>
+// NTS: streaming stores (the frame loads stay plain: neighbouring tiles share them)
+template <typename T, int TX, int TY, bool MU, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g, const int lz,
                                                     const FusedSrc<T> fs, const AmpPack<T, 2> amps,
@@ -793,7 +830,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
 #pragma unroll
-                    for (int p = 0; p < P; ++p) dst[(int64_t)(i * P + p) * g.n + c] = out[i][p];
+                    for (int p = 0; p < P; ++p) st_stream<NTS>(&dst[(int64_t)(i * P + p) * g.n + c], out[i][p]);
             }
         }
         __syncthreads();
@@ -1068,7 +1105,7 @@ __device__ __forceinline__ void dev_encode(const float (&f)[Lat<D>::Q][Lat<D>::P
         }
 }
 
-template <int D, typename H, bool GH>
+template <int D, typename H, bool GH, bool NTS = false>
 __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
                                                   const float (&Sp)[Lat<D>::P], bool any_src, float omega,
                                                   bool tau_half, const float (&rho)[Lat<D>::P],
@@ -1079,9 +1116,9 @@ __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][La
     H code[DevSlots<D, GH>::N];
     dev_encode<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half, rho, K, M, code);
 #pragma unroll
-    for (int q = 0; q < P + D; ++q) Mout[(int64_t)q * n + c] = M[q];
+    for (int q = 0; q < P + D; ++q) st_stream<NTS>(&Mout[(int64_t)q * n + c], M[q]);
 #pragma unroll
-    for (int sl = 0; sl < DevSlots<D, GH>::N; ++sl) Dout[(int64_t)sl * n + c] = code[sl];
+    for (int sl = 0; sl < DevSlots<D, GH>::N; ++sl) st_stream<NTS>(&Dout[(int64_t)sl * n + c], code[sl]);
 }
 
 template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
@@ -1160,7 +1197,8 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
 // formulas as dev_load, so the result equals k_step_dev bit for bit.
 constexpr int TXD = 64, TYD = 4;
 
-template <typename H, bool GH, int RM, bool MU>
+// NTS: streaming stores (the window, code and medium loads stay plain)
+template <typename H, bool GH, int RM, bool MU, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Din, float* Mout, H* Dout,
                                                   const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                   const Geo g, const int lz, const SrcArgs<float> s,
@@ -1296,8 +1334,8 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
                 for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
                 add_mu_source<D, float>(K, cl2, dl, Sp);
             }
-            dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c, Mout,
-                                        Dout);
+            dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c,
+                                             Mout, Dout);
         }
         __syncthreads();
     }

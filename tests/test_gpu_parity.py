@@ -117,6 +117,29 @@ def test_temporal_blocking_3d_bitwise(prec, shape, mu):
 
 
 @pytest.mark.parametrize("mu", [False, True])
+@pytest.mark.parametrize("shape", [(40, 24, 20), (33, 17, 37), (70, 9, 5)])
+def test_streaming_cache_policy_bitwise(shape, mu):
+    """The 3D step kernels with streaming (non-temporal) loads and stores of
+    the state -- the choice for lattices larger than the last-level cache --
+    give the same bits as with plain loads and stores: plain FP64, FP32 and
+    FP16 storage under AA and pull streaming, the fused FP64 and FP32 pairs,
+    and the z-marching kernel in every 16-bit format, with sources and mu."""
+    p = random_problem(3, shape, seed=sum(shape) + 23, mu=mu, nsteps=17)
+    cases = [("f64", "aa", {}), ("f64", "pull", {"LBEM_FUSE3": 1}), ("f64", "pull", {"LBEM_FUSE3": 2}),
+             ("f32", "aa", {}), ("f32", "pull", {"LBEM_FUSE3": 1}), ("f32", "pull", {"LBEM_FUSE3": 2}),
+             ("f16", "aa", {}), ("f16", "pull", {})] + [(q, "pull", {"LBEM_DEV3Z": 1}) for q in LOWP]
+    for prec, st, env in cases:
+        announce(f"streaming cache policy {prec} {st} {shape} mu={mu} {env}")
+        ref = gpu_run(p, 17, prec, st, env=dict(env, LBEM_NT=0))
+        got = gpu_run(p, 17, prec, st, env=dict(env, LBEM_NT=1))
+        assert ref.steps_per_launch == got.steps_per_launch
+        a, b = ref.get_state(), got.get_state()
+        assert a.shape == b.shape and np.array_equal(a, b), (prec, st, env)
+        ref.close()
+        got.close()
+
+
+@pytest.mark.parametrize("mu", [False, True])
 @pytest.mark.parametrize("shape", [(40, 24, 20), (70, 9, 5), (33, 17, 37), (5, 3, 7), (128, 4, 2)])
 def test_deviation_two_step_kernel_bitwise(shape, mu):
     """The two-step 3D deviation kernel (decode, collide, encode and decode
