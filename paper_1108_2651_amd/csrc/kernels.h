@@ -1121,7 +1121,8 @@ __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][La
     for (int sl = 0; sl < DevSlots<D, GH>::N; ++sl) st_stream<NTS>(&Dout[(int64_t)sl * n + c], code[sl]);
 }
 
-template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX>
+// NTS: streaming stores of the state (the gathered loads stay plain)
+template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
@@ -1163,8 +1164,8 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
             add_mu_source<D, float>(K, cl2, dl, Sp);
         }
         if constexpr (!BX) {
-            dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c, Mout,
-                                        Dout);
+            dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c,
+                                             Mout, Dout);
         } else {
             float Jn[P];
             const bool ade = bc.ade != nullptr;

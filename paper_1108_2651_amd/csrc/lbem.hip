@@ -133,8 +133,8 @@ struct lbem_s {
     int2* fsrc_ent;
     void* fsrc_val;
     int64_t nfsrc;
-    // 3D steps with the streaming cache policy on the stored state (lattices
-    // whose state a launch touches exceeds the last-level cache)
+    // single steps with the streaming cache policy on the stored state
+    // (lattices whose state a launch touches exceeds the last-level cache)
     int nts;
     // 3D deviation kernel marching along z (column tiles x z-chunks)
     int zmarch, zlz;
@@ -332,7 +332,7 @@ struct PlainImpl : Impl {
         s.val = (const T*)h->src_val;
         s.amp = amp;
         const double om = 1.0 / h->cfg.tau;
-        if constexpr (D == 3 && !BX) {
+        if constexpr (!BX) {
             if (h->nts) {
                 hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX, S, true>), dim3(h->geo.nblocks),
                                    dim3(NT), 0, h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo,
@@ -457,6 +457,15 @@ struct DevImpl : Impl {
         s.ent = h->src_ent;
         s.val = (const float*)h->src_val;
         s.amp = amp;
+        if constexpr (!BX) {
+            if (h->nts) {
+                hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX, true>), dim3(h->geo.nblocks), dim3(NT), 0,
+                                   h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                                   (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
+                                   (int)(h->cfg.tau == 0.5), ext_of(h));
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
@@ -747,14 +756,16 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     make_geo(h);
     make_fused_geo(h);
     make_zmarch_geo(h);
-    // Measured on 3D lattices: streaming loads/stores slow a launch whose
-    // state fits the 256 MB Infinity Cache (by up to 1.8x) and speed it up by
-    // 2-8 % beyond about 1.5 times that; the copies a step touches count
-    // (one with AA streaming, two with pull).
+    // Measured: streaming loads/stores slow a launch whose state fits the
+    // 256 MB Infinity Cache (by up to 1.8x) and speed it up beyond that: in 3D
+    // from about 1.5 times the cache on (2-10 %; at 344 MB still 9 % slower),
+    // in 2D as soon as the state leaves it (FP32 AA 16 % at 335 MB, 17 % at
+    // 1.3 GB).  The copies a step touches count (one with AA streaming, two
+    // with pull).  The multi-step 2D kernel keeps plain accesses.
     {
         const double touched = (double)s.pop_one * (h->streaming == LBEM_STREAM_AA ? 1 : 2);
-        const double lim = (double)env_int("LBEM_NT_MIB", 384) * (1 << 20);
-        h->nts = h->D == 3 ? env_int("LBEM_NT", touched > lim ? 1 : 0) != 0 : 0;
+        const double lim = (double)env_int("LBEM_NT_MIB", h->D == 2 ? 256 : 384) * (1 << 20);
+        h->nts = env_int("LBEM_NT", touched > lim ? 1 : 0) != 0;
     }
     h->impl = make_impl(h->D, h->prec);
     if (h->impl && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
