@@ -537,7 +537,8 @@ struct AmpPack {
 };
 
 // O32: every population plane fits 2^32 bytes (32-bit element offsets)
-template <typename T, int NS, int TY, bool MU, bool O32>
+// NTS: streaming stores of the state (lattices beyond the last-level cache)
+template <typename T, int NS, int TY, bool MU, bool O32, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g,
                                                     const FusedSrc<T> fs, const AmpPack<T, NS> amps,
@@ -675,8 +676,8 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
                     const int gcell = gx + g.nx * gy;
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
-                        if constexpr (O32) at32(dst + (int64_t)i * g.n, (unsigned)gcell) = o[i][0];
-                        else dst[(int64_t)i * g.n + gcell] = o[i][0];
+                        if constexpr (O32) st_stream<NTS>(&at32(dst + (int64_t)i * g.n, (unsigned)gcell), o[i][0]);
+                        else st_stream<NTS>(&dst[(int64_t)i * g.n + gcell], o[i][0]);
                     }
                 }
             } else {

@@ -241,8 +241,13 @@ static hipError_t go_fused_ntm(lbem_s* h, const T* src, T* dst, const double* am
     fs.val = (const T*)h->fsrc_val;
     AmpPack<T, NS> a;
     for (int j = 0; j < NS; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
-    // 32-bit element offsets while one population plane fits 2^32 bytes
-    if ((uint64_t)h->n * sizeof(T) <= (1ull << 32))
+    // 32-bit element offsets while one population plane fits 2^32 bytes;
+    // streaming stores beyond the last-level cache (2-3 % there)
+    if ((uint64_t)h->n * sizeof(T) <= (1ull << 32) && h->nts)
+        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, true, true>), dim3(h->fgeo.nblocks), dim3(NT), 0,
+                           h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a,
+                           (T)(1.0 / h->cfg.tau), (int)(h->cfg.tau == 0.5));
+    else if ((uint64_t)h->n * sizeof(T) <= (1ull << 32))
         hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, true>), dim3(h->fgeo.nblocks), dim3(NT), 0, h->stream,
                            src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, (T)(1.0 / h->cfg.tau),
                            (int)(h->cfg.tau == 0.5));
@@ -761,7 +766,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     // from about 1.5 times the cache on (2-10 %; at 344 MB still 9 % slower),
     // in 2D as soon as the state leaves it (FP32 AA 16 % at 335 MB, 17 % at
     // 1.3 GB).  The copies a step touches count (one with AA streaming, two
-    // with pull).  The multi-step 2D kernel keeps plain accesses.
+    // with pull).
     {
         const double touched = (double)s.pop_one * (h->streaming == LBEM_STREAM_AA ? 1 : 2);
         const double lim = (double)env_int("LBEM_NT_MIB", h->D == 2 ? 256 : 384) * (1 << 20);

@@ -119,12 +119,13 @@ def test_temporal_blocking_3d_bitwise(prec, shape, mu):
 @pytest.mark.parametrize("mu", [False, True])
 @pytest.mark.parametrize("shape", [(40, 24, 20), (33, 17, 37), (70, 9, 5), (96, 40, 1), (100, 37, 1)])
 def test_streaming_cache_policy_bitwise(shape, mu):
-    """The single-step kernels with streaming (non-temporal) loads and stores
+    """The step kernels with streaming (non-temporal) loads and stores
     of the state -- the choice for lattices larger than the last-level cache --
     give the same bits as with plain loads and stores: plain FP64, FP32 and
-    FP16 storage under AA and pull streaming, the fused FP64 and FP32 3D
-    pairs, and the gather and z-marching deviation kernels in every 16-bit
-    format, in 2D and 3D, with sources and mu."""
+    FP16 storage under AA and pull streaming, the fused FP64 and FP32 kernels
+    (2D: two and four steps; 3D: pairs), and the gather and z-marching
+    deviation kernels in every 16-bit format, in 2D and 3D, with sources and
+    mu."""
     dim = 3 if shape[2] > 1 else 2
     p = random_problem(dim, shape, seed=sum(shape) + 23, mu=mu, nsteps=17)
     if dim == 3:
@@ -133,8 +134,9 @@ def test_streaming_cache_policy_bitwise(shape, mu):
                  ("f16", "aa", {}), ("f16", "pull", {})]
         cases += [(q, "pull", {"LBEM_DEV3Z": z}) for q in LOWP for z in (0, 1)]
     else:
-        cases = [("f64", "aa", {}), ("f64", "pull", {"LBEM_FUSE": 1}), ("f32", "aa", {}),
-                 ("f32", "pull", {"LBEM_FUSE": 1}), ("f16", "aa", {}), ("f16", "pull", {})]
+        cases = [("f64", "aa", {}), ("f64", "pull", {"LBEM_FUSE": 1}), ("f64", "pull", {"LBEM_FUSE": 2}),
+                 ("f32", "aa", {}), ("f32", "pull", {"LBEM_FUSE": 1}), ("f32", "pull", {"LBEM_FUSE": 2}),
+                 ("f32", "pull", {"LBEM_FUSE": 4}), ("f16", "aa", {}), ("f16", "pull", {})]
         cases += [(q, "pull", {}) for q in LOWP]
     for prec, st, env in cases:
         announce(f"streaming cache policy {prec} {st} {shape} mu={mu} {env}")
