@@ -425,7 +425,7 @@ __device__ __forceinline__ void st_stream(S* p, S v)
 }
 
 // NTS: streaming loads and stores of the populations (each is read and written
-// once per launch; large 3D lattices, no cell extras)
+// once per launch; lattices beyond the last-level cache)
 template <int D, typename T, int RM, int WM, int VEC, bool MU, bool BX, typename S = T, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T* __restrict__ cl2a,
                                                   const T* __restrict__ dlnmu, const Geo g,
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 if (BX && RM == R_PULL && ((C.wall >> i) & 1u)) {
-                    const T v = ld_pop<T>(src[(int64_t)(opp(D, i) * P + p) * g.n + C.c]);
+                    const T v = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(opp(D, i) * P + p) * g.n + C.c]));
                     f[i][p] = wall_negates<D>(bc, i, p) ? -v : v;
                 } else {
                     f[i][p] = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]));
@@ -1022,7 +1022,7 @@ __device__ __forceinline__ float dev_load(const float* M, const H* Dv, int64_t n
 
 // Encode a post-collision state: its moments (FP32) and the scaled 16-bit
 // deviations from the equilibrium of those moments.
-template <int D, typename H, bool GH>
+template <int D, typename H, bool GH, bool NTS = false>
 __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::P], float cl2, float wc0,
                                           int64_t n, int c, float* Mout, H* Dout)
 {
@@ -1034,9 +1034,9 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
 #pragma unroll
     for (int b = 0; b < D; ++b) Bb2[b] = D == 2 ? K2[b] : 0.5f * K2[b];
 #pragma unroll
-    for (int p = 0; p < P; ++p) Mout[(int64_t)p * n + c] = Lam2[p];
+    for (int p = 0; p < P; ++p) st_stream<NTS>(&Mout[(int64_t)p * n + c], Lam2[p]);
 #pragma unroll
-    for (int b = 0; b < D; ++b) Mout[(int64_t)(P + b) * n + c] = Bb2[b];
+    for (int b = 0; b < D; ++b) st_stream<NTS>(&Mout[(int64_t)(P + b) * n + c], Bb2[b]);
     float m = 0.f;
 #pragma unroll
     for (int p = 0; p < P; ++p) m = fmaxf(m, fabsf(Lam2[p]));
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void dev_store(const float (&out)[Lat<D>::Q][Lat<D>::
             const int sl = dev_slot<D, GH>(i, p);
             if (sl < 0) continue;
             const float d = out[i][p] - dev_eq<D>(i, p, Lam2, Bb2, wc0);
-            Dout[(int64_t)sl * n + c] = f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm)));
+            st_stream<NTS>(&Dout[(int64_t)sl * n + c], f2h<H>(sat16<H>(d * (i == 0 ? inv0 : invm))));
         }
 }
 
@@ -1184,7 +1184,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
 #pragma unroll
                     for (int p = 0; p < P; ++p) out[i][p] *= k;
             }
-            dev_store<D, H, GH>(out, cl2, wc0, g.n, C.c, Mout, Dout);
+            dev_store<D, H, GH, NTS>(out, cl2, wc0, g.n, C.c, Mout, Dout);
         }
     }
 }

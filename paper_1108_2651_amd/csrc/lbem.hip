@@ -337,13 +337,11 @@ struct PlainImpl : Impl {
         s.val = (const T*)h->src_val;
         s.amp = amp;
         const double om = 1.0 / h->cfg.tau;
-        if constexpr (!BX) {
-            if (h->nts) {
-                hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX, S, true>), dim3(h->geo.nblocks),
-                                   dim3(NT), 0, h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo,
-                                   s, (T)om, (int)(h->cfg.tau == 0.5), ext_of(h));
-                return hipGetLastError();
-            }
+        if (h->nts) {
+            hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX, S, true>), dim3(h->geo.nblocks), dim3(NT), 0,
+                               h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
+                               (int)(h->cfg.tau == 0.5), ext_of(h));
+            return hipGetLastError();
         }
         hipLaunchKernelGGL((k_step_plain<D, T, RM, WM, V, MU, BX, S>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->geo, s, (T)om,
@@ -462,14 +460,12 @@ struct DevImpl : Impl {
         s.ent = h->src_ent;
         s.val = (const float*)h->src_val;
         s.amp = amp;
-        if constexpr (!BX) {
-            if (h->nts) {
-                hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX, true>), dim3(h->geo.nblocks), dim3(NT), 0,
-                                   h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
-                                   (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
-                                   (int)(h->cfg.tau == 0.5), ext_of(h));
-                return hipGetLastError();
-            }
+        if (h->nts) {
+            hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX, true>), dim3(h->geo.nblocks), dim3(NT), 0,
+                               h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                               (const float*)h->dlnmu, h->geo, s, (float)(1.0 / h->cfg.tau),
+                               (int)(h->cfg.tau == 0.5), ext_of(h));
+            return hipGetLastError();
         }
         hipLaunchKernelGGL((k_step_dev<D, H, GH, RM, V, MU, BX>), dim3(h->geo.nblocks), dim3(NT), 0,
                            h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,

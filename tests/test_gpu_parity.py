@@ -7,6 +7,8 @@ sqrt(sum eps_abs|dE|^2 + |dB|^2/mu) / sqrt(sum eps_abs|E|^2 + |B|^2/mu)
 both) with each field's relative L2 reported and held
 to twice that: a field's own norm can pass through a temporal node (E in a
 resonant periodic box), where its relative error is not meaningful."""
+import os
+
 import numpy as np
 import pytest
 
@@ -147,6 +149,41 @@ def test_streaming_cache_policy_bitwise(shape, mu):
         assert a.shape == b.shape and np.array_equal(a, b), (prec, st, env)
         ref.close()
         got.close()
+
+
+@pytest.mark.parametrize("shape", [(30, 22, 18), (96, 40, 1)])
+def test_streaming_cache_policy_bitwise_cell_extras(shape):
+    """The same with the cell extras on (PEC/PMC walls, an absorbing layer and
+    a dispersion pole): the step kernels that handle them give the same bits
+    with and without streaming loads and stores, plain and 16-bit formats."""
+    from paper_1108_2651_amd import lbem
+    dim = 3 if shape[2] > 1 else 2
+    p = random_problem(dim, shape, seed=sum(shape) + 29, nsteps=12)
+    sigma = np.linspace(0.0, 0.3, p.n)
+    for prec in ("f64", "f32", "f16", "f16dev", "f16ghost", "bf16ghost"):
+        blobs = []
+        for nt in ("0", "1"):
+            announce(f"streaming cache policy, cell extras: {prec} {shape} LBEM_NT={nt}")
+            old = os.environ.get("LBEM_NT")
+            os.environ["LBEM_NT"] = nt       # read when the handle is created
+            try:
+                s = lbem.Solver(dim, shape, prec, w0_vac=p.w0_vac, streaming="pull")
+            finally:
+                if old is None:
+                    os.environ.pop("LBEM_NT", None)
+                else:
+                    os.environ["LBEM_NT"] = old
+            s.set_boundary(0, "pec")
+            s.set_boundary(1, "pmc")
+            s.set_medium(p.eps_r)
+            s.set_absorber(sigma)
+            s.set_dispersion(np.linspace(0.0, 0.02, p.n), 0.01, 0.05)
+            s.init_fields(p.E0, p.B0)
+            s.set_source(p.src_comp, p.src_cells, p.src_weights)
+            s.step(12, p.amp[:12])
+            blobs.append(s.get_state())
+            s.close()
+        assert np.array_equal(blobs[0], blobs[1]), prec
 
 
 @pytest.mark.parametrize("mu", [False, True])
