@@ -391,8 +391,8 @@ template <>
 __device__ __forceinline__ __half st_pop<__half, float>(float v) { return __float2half_rn(v); }
 
 // Global access with the streaming (non-temporal) cache policy when NTS is
-// set, plain access otherwise; the values are the same either way.  A 3D step
-// on a lattice larger than the last-level cache touches each stored value once
+// set, plain access otherwise; the values are the same either way.  A step on
+// a lattice larger than the last-level cache touches each stored value once
 // per launch, and marking those lines for early eviction keeps the caches for
 // the halo lines that neighbouring tiles share.  Loads that neighbouring tiles
 // share are never marked: those lose their reuse.
