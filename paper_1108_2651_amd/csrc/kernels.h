@@ -537,8 +537,10 @@ struct AmpPack {
 };
 
 // O32: every population plane fits 2^32 bytes (32-bit element offsets)
-// NTS: streaming stores of the state (lattices beyond the last-level cache)
-template <typename T, int NS, int TY, bool MU, bool O32, bool NTS = false>
+// NTS: streaming stores of the state (lattices beyond the last-level cache).
+// TH: tau = 1/2 known when compiling (the reflection collision, whatever
+// tau_half says), else tau_half chooses at run time.
+template <typename T, int NS, int TY, bool MU, bool O32, bool NTS, bool TH>
 __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g,
                                                     const FusedSrc<T> fs, const AmpPack<T, NS> amps,
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
                     ldl[0][k] = dl0[j][0];
                     ldl[MU ? 1 : 0][k] = dl0[j][1];
                 }
-                collide<2, T>(fv0[j], cl0[j], Sp, has_src || MU, omega, tau_half != 0, rho, K, o);
+                collide<2, T>(fv0[j], cl0[j], Sp, has_src || MU, omega, TH || tau_half != 0, rho, K, o);
                 lc[k] = cl0[j];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) lp[0][i][k] = o[i][0];
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
                 add_mu_source<2, T>(K, cl2, dl, Sp);
             }
             T o[Q][1];
-            collide<2, T>(fv, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, o);
+            collide<2, T>(fv, cl2, Sp, has_src || MU, omega, TH || tau_half != 0, rho, K, o);
             if (st == NS - 1) {
                 const int gx = x0 + fx, gy = y0 + fy;    // inside the tile: no wrap needed
                 if (gx < g.nx && gy < g.ny) {

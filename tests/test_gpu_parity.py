@@ -233,6 +233,8 @@ def test_tau_not_half_every_format(prec):
     gather, z-marching and multi-step kernels."""
     p = random_problem(2, (40, 24, 1), seed=33, mu=True, nsteps=80)
     compare(p, 80, prec, "pull", tau=0.8)
+    if prec == "f32":                   # four fused steps per launch (general-tau instantiation)
+        compare(p, 80, prec, "pull", tau=0.8, env={"LBEM_FUSE": 4, "LBEM_FUSE_TY": 8})
     p3 = random_problem(3, (20, 12, 10), seed=34, mu=True, nsteps=40)
     envs = [None, {"LBEM_FUSE3": 2}] if prec == "f32" else [None, {"LBEM_DEV3Z": 1}, {"LBEM_DEV3F": 1}]
     for env in envs:
