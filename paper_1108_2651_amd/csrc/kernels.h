@@ -703,8 +703,9 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // only then stores plane zz's in-plane components into the single LDS frame
 // (one frame instead of two keeps three blocks per CU).  Every update is the
 // same collide() as the single-step kernel: bit-identical.
-// NTS: streaming stores (the frame loads stay plain: neighbouring tiles share them)
-template <typename T, int TX, int TY, bool MU, bool NTS = false>
+// NTS: streaming stores (the frame loads stay plain: neighbouring tiles share
+// them).  TH: tau = 1/2 known when compiling, as for the 2D kernel.
+template <typename T, int TX, int TY, bool MU, bool NTS, bool TH>
 __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g, const int lz,
                                                     const FusedSrc<T> fs, const AmpPack<T, 2> amps,
@@ -780,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
                 for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
                 add_mu_source<D, T>(K, cl2, dl, Sp);
             }
-            collide<D, T>(f, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, out);
+            collide<D, T>(f, cl2, Sp, has_src || MU, omega, TH || tau_half != 0, rho, K, out);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int sl = ipl(i);
@@ -829,7 +830,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
                     for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + c];
                     add_mu_source<D, T>(K, cl2, dl, Sp);
                 }
-                collide<D, T>(f, cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, out);
+                collide<D, T>(f, cl2, Sp, has_src || MU, omega, TH || tau_half != 0, rho, K, out);
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
 #pragma unroll

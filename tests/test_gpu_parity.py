@@ -223,6 +223,7 @@ def test_tau_not_half():
     compare(p, 80, "f64", tau=0.8)
     p3 = random_problem(3, (12, 10, 8), seed=4, nsteps=40)
     compare(p3, 40, "f64", tau=1.3)
+    compare(p3, 40, "f64", "pull", tau=1.3, env={"LBEM_FUSE3": 2})   # general-tau fused pair
 
 
 @pytest.mark.parametrize("prec", ["f32"] + LOWP)
