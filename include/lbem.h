@@ -184,7 +184,9 @@ int lbem_steps_per_launch(lbem_t h);
 size_t lbem_state_bytes(lbem_t h);
 
 /* Write the state blob into buf (bytes >= lbem_state_bytes).  on_device == 0:
- * host memory, else device memory on the handle's device.  Synchronises.
+ * host memory, else device memory on the handle's device.  Synchronises.  The
+ * blob is a function of the handle's state alone: alignment padding inside it
+ * is zero, so two handles at the same state write the same bytes.
  * Errors: EINVAL (NULL, too small), ESTATE (no fields yet), EDEVICE. */
 int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device);
 
