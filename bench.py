@@ -279,7 +279,7 @@ def size_sweep(steps: int = 100, warmup: int = 5) -> list:
 
 
 SERVING_CONFIG = ("Poisson arrivals; 70% 2D 64^2-1024^2, 30% 3D 32^3-128^3; smooth eps in [1,4]; "
-                  "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 50 steps per tick; "
+                  "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 100 steps per tick; "
                   "latency = arrival to E,B on the host")
 
 
@@ -287,7 +287,7 @@ def serving_run(rate: float, count: int) -> dict:
     """The continuous-batching serving mix at `rate` requests/s."""
     from paper_1108_2651_amd import serve as SV
     reqs = SV.make_requests(count=count, rate=rate)
-    rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=50, workers=6)
+    rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=100, workers=6)
     return dict(requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
                 p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
                 mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,

@@ -397,7 +397,7 @@ def make_requests(count: int = 2000, rate: float = 200.0, seed: int | None = Non
     return out
 
 
-def serve(requests, budget_bytes=2 << 30, max_slots=256, steps_per_tick=50, workers=4,
+def serve(requests, budget_bytes=2 << 30, max_slots=256, steps_per_tick=100, workers=4,
           keep_results=False) -> Report:
     ex = GpuExecutor(max_slots, steps_per_tick, workers=workers)
     try:
