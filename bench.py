@@ -287,7 +287,7 @@ def serving_run(rate: float, count: int) -> dict:
     """The continuous-batching serving mix at `rate` requests/s."""
     from paper_1108_2651_amd import serve as SV
     reqs = SV.make_requests(count=count, rate=rate)
-    rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=100, workers=6)
+    rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=100, workers=10)
     return dict(requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
                 p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
                 mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,
