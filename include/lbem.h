@@ -57,12 +57,17 @@ typedef enum {
     LBEM_F16DEV = 2,   /* FP32 conserved moments + FP16 deviations from the local
                           equilibrium, scaled by a power of two per velocity;
                           all collision arithmetic in FP32                        */
-    LBEM_BF16DEV = 3,  /* as LBEM_F16DEV with BF16 deviations                     */
+    LBEM_BF16DEV = 3,  /* as LBEM_F16DEV with BF16 deviations.  NOT within the
+                          1e-3 relative field error of the FP16 formats: BF16
+                          keeps an 8-bit significand, and the measured error
+                          against the FP64 solution is 1.2e-3 - 3.6e-3 per
+                          field (1000-2000 steps, smooth media with sources)   */
     LBEM_F16GHOST = 4, /* FP32 conserved moments + FP16 ghost coordinates: only the
                           (Q-1)P - D moving deviations that the zero-moment
                           constraints leave free are stored (2D 2 of 5, 3D 15 of
                           21 per cell); the rest follow from the constraints    */
-    LBEM_BF16GHOST = 5, /* as LBEM_F16GHOST with BF16 ghost coordinates          */
+    LBEM_BF16GHOST = 5, /* as LBEM_F16GHOST with BF16 ghost coordinates; NOT
+                          within 1e-3 (same band as LBEM_BF16DEV)               */
     LBEM_F16 = 6       /* plain FP16 populations, FP32 medium and arithmetic
                           (rounded to nearest on store); single steps, pull or
                           AA.  A bandwidth reference: its rounding is relative
@@ -135,7 +140,10 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B);
  * (eq. LBE), eps_abs = eps_r/c_vac^2.  ESTATE before lbem_set_medium. */
 int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weight, int64_t m);
 
-/* Enqueue nsteps time steps.  amp (host, nsteps doubles, may be NULL = no
+/* Enqueue nsteps time steps of the lattice-BGK equation (eq. LBE): each step
+ * forms the moments (eqs. relate.1-2), relaxes to the equilibrium (eq.
+ * distrib.func) with the BGK collision and the tensor source (eq. COLLI), and
+ * streams (eq. STREAM).  amp (host, nsteps doubles, may be NULL = no
  * source) gives the source amplitude of each step: step k of this call uses
  * amp[k] at time t0 + k.  ESTATE before lbem_init_fields.  Periodic handles in
  * the plain formats with pull streaming advance several steps per launch
@@ -144,17 +152,23 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
  * not depend on this choice (bit for bit). */
 int lbem_step(lbem_t h, int64_t nsteps, const double* amp);
 
-/* E and B at the current time (3*n doubles each, component-major).  With
+/* E and B at the current time (3*n doubles each, component-major), recovered
+ * from the zeroth and first moments of the populations (eqs. relate.1-2: E
+ * from Lambda = c^2 sum_i g_i by the Levi-Civita contraction of the Maxwell
+ * section, B = K, the contracted first moment).  With
  * on_device == 0 they are host pointers, else device pointers on the
  * handle's device.  Either pointer may be NULL to skip it.  Synchronises. */
 int lbem_moments(lbem_t h, double* E, double* B, int on_device);
 
 /* FP64 diagnostics at the current time (synchronises):
- *   out[0]  EM energy  sum_x eps_abs |E|^2 + |B|^2/mu_r
+ *   out[0]  EM energy  sum_x eps_abs |E|^2 + |B|^2/mu_r  (the energy of
+ *           Subsection "Heterogeneous media", sum of B^2 + E^2/c^2, with the
+ *           local light speed and permeability)
  *   out[1]  Q_c = sum_x c_L^2 sum_i sum_p g_ip^2 / w_i  (exact invariant of
  *           the scheme at tau = 1/2 with mu == 1, no source, no absorber or
  *           dispersion, periodic or walled faces, uniform anisotropy ratios)
- *   out[2]  sum_x (div_h B)^2, periodic central differences (also with walls)
+ *   out[2]  sum_x (div_h B)^2, periodic central differences (also with walls):
+ *           the solenoidal constraint of the Maxwell section, div B = 0
  *   out[3]  sum_x |B|^2
  * ENONFINITE if any of them is NaN or Inf (the values are still written). */
 int lbem_energy(lbem_t h, double out[4]);

@@ -96,16 +96,14 @@ class PSMaxwell:
         return E.reshape(3, -1), B.reshape(3, -1)
 
 
-def divb_spectral_error(B, shape, kernel: str = "l2", sigma: float = 2.0, k0=None):
-    """Spectral divergence error of eq. error.def for a periodic field B on
-    the unit box (physical wavenumbers 2 pi m):
+def divb_spectral_error(B, shape):
+    """Spectral divergence error of eq. error.def with the unit kernel F = 1,
+    for a periodic field B on the unit box (physical wavenumbers 2 pi m):
 
-        eps(k) = sum_k' F(k,k') |i k'.B(k')| / sum_k' F(k,k') |B(k')|
+        eps = sum_k |i k . B(k)| / sum_k |B(k)|,   |B(k)| = sqrt(sum_c |B_c(k)|^2)
 
-    kernel 'l2': F = 1 (returns a scalar); 'radial': F = exp(-(|k|-|k'|)^2 /
-    (2 sigma^2)) evaluated at |k| = k0 (a number, in 2 pi units);
-    'vector': F = exp(-|k-k'|^2/(2 sigma^2)) at the vector k0.  sigma is in
-    wavenumber bins (units of 2 pi)."""
+    (the paper's kernel width is unspecified; F = 1 is the choice every use
+    here makes).  B is (>= dim, n); only the in-lattice components enter."""
     nx, ny, nz = shape
     dim = 2 if nz == 1 else 3
     grid = (ny, nx) if dim == 2 else (nz, ny, nx)
@@ -116,15 +114,5 @@ def divb_spectral_error(B, shape, kernel: str = "l2", sigma: float = 2.0, k0=Non
     kv = [2.0 * np.pi * mm[dim - 1 - c] for c in range(dim)]
     div = np.abs(sum(1j * kv[c] * Bk[c] for c in range(dim)))
     mag = np.sqrt(sum(np.abs(Bk[c]) ** 2 for c in range(dim)))
-    if kernel == "l2":
-        F = 1.0
-    elif kernel == "radial":
-        kabs = np.sqrt(sum((mm[c]) ** 2 for c in range(dim)))
-        F = np.exp(-((kabs - k0) ** 2) / (2.0 * sigma ** 2))
-    elif kernel == "vector":
-        d2 = sum((mm[dim - 1 - c] - k0[c]) ** 2 for c in range(dim))
-        F = np.exp(-d2 / (2.0 * sigma ** 2))
-    else:
-        raise ValueError(kernel)
-    den = np.sum(F * mag)
-    return float(np.sum(F * div) / den) if den > 0 else 0.0
+    den = np.sum(mag)
+    return float(np.sum(div) / den) if den > 0 else 0.0

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <shared_mutex>
 #include <vector>
 
 #include "../../include/lbem.h"
@@ -19,6 +21,13 @@ namespace {
 enum Layout { LAYOUT_NATURAL = 0, LAYOUT_PULL_PENDING = 1, LAYOUT_AA_SWAPPED = 2 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Graph capture of the batched kernels (lbem_batch_create) holds this lock
+// exclusively; the entry points that allocate or free device memory, or
+// create and destroy HIP objects, hold it shared.  No allocation or free of
+// this library then runs while a graph is captured and instantiated.
+std::shared_mutex g_api_mu;
+#define API_SHARED std::shared_lock<std::shared_mutex> api_lock_(g_api_mu)
 
 int env_int(const char* name, int dflt)
 {
@@ -156,8 +165,21 @@ struct lbem_s {
     int64_t t;
     bool have_medium, have_fields;
     Impl* impl;
-    hipEvent_t sync_ev;      // orders this handle's stream against batch ticks
+    hipEvent_t sync_ev;      // set-up work on this handle's stream before a batch tick
+    hipEvent_t tick_ev;      // end of the last batch tick that advanced this handle
+    bool tick_pending;       // this handle's stream has not yet waited on tick_ev
 };
+
+// Work on the handle's own stream that touches its state follows the batch
+// ticks that advanced it.  The wait is added here, at the handle's next use,
+// not when the tick is enqueued: the stream may be shared with other
+// handles' set-up, which need not wait for the tick.
+static hipError_t follow_ticks(lbem_s* h)
+{
+    if (!h->tick_pending) return hipSuccess;
+    h->tick_pending = false;
+    return hipStreamWaitEvent(h->stream, h->tick_ev, 0);
+}
 
 #define HIP_OK(x)                                  \
     do {                                           \
@@ -715,6 +737,7 @@ const char* lbem_strerror(int code)
 
 int lbem_create(const lbem_config* cfg, lbem_t* out)
 {
+    API_SHARED;
     if (!out) return LBEM_EINVAL;
     *out = nullptr;
     if (!valid_cfg(cfg)) return LBEM_EINVAL;
@@ -759,7 +782,8 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     }
     h->scratch = (double*)p;
     h->nb_diag = blocks1(h->n);
-    if (hipMalloc((void**)&h->partials, ((size_t)h->nb_diag * 4 + 4) * sizeof(double)) != hipSuccess) {
+    if (hipMallocAsync((void**)&h->partials, ((size_t)h->nb_diag * 4 + 4) * sizeof(double), h->stream) !=
+        hipSuccess) {
         if (h->own_mem) (void)hipFree(h->arena);
         delete h;
         return LBEM_ENOMEM;
@@ -784,12 +808,14 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
         h->nts = env_int("LBEM_NT", touched > lim ? 1 : 0) != 0;
     }
     h->impl = make_impl(h->D, h->prec);
-    if (h->impl && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
+    if (h->impl && (hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess ||
+                    hipEventCreateWithFlags(&h->tick_ev, hipEventDisableTiming) != hipSuccess)) {
+        if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
         delete h->impl;
         h->impl = nullptr;
     }
     if (!h->impl) {
-        (void)hipFree(h->partials);
+        (void)hipFreeAsync(h->partials, h->stream);
         if (h->own_mem) (void)hipFree(h->arena);
         delete h;
         return LBEM_ENOMEM;
@@ -963,15 +989,19 @@ static int build_fused_source(lbem_s* h, const std::vector<double>& dense)
 int lbem_destroy(lbem_t h)
 {
     if (!h) return LBEM_OK;
+    API_SHARED;
+    (void)follow_ticks(h);
     (void)hipStreamSynchronize(h->stream);
     free_source(h);
     if (h->keep) (void)hipFree(h->keep);
     if (h->ade) (void)hipFree(h->ade);
     if (h->pol) (void)hipFree(h->pol);
     if (h->ra) (void)hipFree(h->ra);
-    if (h->partials) (void)hipFree(h->partials);
+    // stream-ordered: returns the memory without waiting for the whole device
+    if (h->partials) (void)hipFreeAsync(h->partials, h->stream);
     if (h->own_mem && h->arena) (void)hipFree(h->arena);
     if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
+    if (h->tick_ev) (void)hipEventDestroy(h->tick_ev);
     delete h->impl;
     delete h;
     return LBEM_OK;
@@ -986,14 +1016,21 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
         for (int64_t c = 0; c < n; ++c)
             if (mu_r[c] != 1.0) { nonunit_mu = true; break; }
     if (nonunit_mu && !h->cfg.mu_varies) return LBEM_EINVAL;
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
+    // staging buffers are stream-ordered allocations: freeing them does not
+    // wait for other streams' work (batch ticks in flight)
     double *deps = nullptr, *dmu = nullptr;
     int* dflag = nullptr;
     int flag = 0, rc = LBEM_OK;
-    if (hipMalloc((void**)&deps, n * 8) != hipSuccess) return LBEM_ENOMEM;
-    if (mu_r && hipMalloc((void**)&dmu, n * 8) != hipSuccess) { (void)hipFree(deps); return LBEM_ENOMEM; }
-    if (hipMalloc((void**)&dflag, sizeof(int)) != hipSuccess) {
-        (void)hipFree(deps);
-        if (dmu) (void)hipFree(dmu);
+    if (hipMallocAsync((void**)&deps, n * 8, h->stream) != hipSuccess) return LBEM_ENOMEM;
+    if (mu_r && hipMallocAsync((void**)&dmu, n * 8, h->stream) != hipSuccess) {
+        (void)hipFreeAsync(deps, h->stream);
+        return LBEM_ENOMEM;
+    }
+    if (hipMallocAsync((void**)&dflag, sizeof(int), h->stream) != hipSuccess) {
+        (void)hipFreeAsync(deps, h->stream);
+        if (dmu) (void)hipFreeAsync(dmu, h->stream);
         return LBEM_ENOMEM;
     }
     hipError_t e = hipMemcpyAsync(deps, eps_r, n * 8, hipMemcpyHostToDevice, h->stream);
@@ -1006,9 +1043,9 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = LBEM_EDEVICE;
     else if (flag) rc = LBEM_EUNSTABLE;
-    (void)hipFree(deps);
-    if (dmu) (void)hipFree(dmu);
-    (void)hipFree(dflag);
+    (void)hipFreeAsync(deps, h->stream);
+    if (dmu) (void)hipFreeAsync(dmu, h->stream);
+    (void)hipFreeAsync(dflag, h->stream);
     h->have_medium = rc == LBEM_OK;
     h->have_fields = false;
     return rc;
@@ -1025,16 +1062,21 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B)
         for (int64_t c = 0; c < n; ++c)
             if (E[c] != 0.0 || E[n + c] != 0.0 || B[2 * n + c] != 0.0) return LBEM_EINVAL;
     }
-    double *dE = nullptr, *dB = nullptr;
-    if (hipMalloc((void**)&dE, 3 * n * 8) != hipSuccess) return LBEM_ENOMEM;
-    if (hipMalloc((void**)&dB, 3 * n * 8) != hipSuccess) { (void)hipFree(dE); return LBEM_ENOMEM; }
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
+    double *dE = nullptr, *dB = nullptr;      // stream-ordered staging (see lbem_set_medium)
+    if (hipMallocAsync((void**)&dE, 3 * n * 8, h->stream) != hipSuccess) return LBEM_ENOMEM;
+    if (hipMallocAsync((void**)&dB, 3 * n * 8, h->stream) != hipSuccess) {
+        (void)hipFreeAsync(dE, h->stream);
+        return LBEM_ENOMEM;
+    }
     hipError_t e = hipMemcpyAsync(dE, E, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dB, B, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = h->impl->init(h, dE, dB);
     if (e == hipSuccess && h->pol) e = hipMemsetAsync(h->pol, 0, pol_bytes(h), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(dE);
-    (void)hipFree(dB);
+    (void)hipFreeAsync(dE, h->stream);
+    (void)hipFreeAsync(dB, h->stream);
     if (e != hipSuccess) return LBEM_EDEVICE;
     h->t = 0;
     h->have_fields = true;
@@ -1055,6 +1097,8 @@ int lbem_set_anisotropy(lbem_t h, const double* fac)
     if (!h || !fac) return LBEM_EINVAL;
     if (h->prec > LBEM_F32 || h->streaming != LBEM_STREAM_PULL) return LBEM_EINVAL;
     if (!h->have_medium) return LBEM_ESTATE;
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
     const int64_t n = h->n;
     const size_t tm = h->prec == LBEM_F64 ? 8 : 4;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
@@ -1090,6 +1134,8 @@ int lbem_set_anisotropy(lbem_t h, const double* fac)
 int lbem_set_dispersion(lbem_t h, const double* wp2, const double* w02, const double* gamma)
 {
     if (!h) return LBEM_EINVAL;
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
     if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
     if (!wp2) {
         if (h->ade) (void)hipFree(h->ade);
@@ -1134,6 +1180,8 @@ int lbem_set_dispersion(lbem_t h, const double* wp2, const double* w02, const do
 int lbem_set_absorber(lbem_t h, const double* sigma)
 {
     if (!h) return LBEM_EINVAL;
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
     if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
     if (!sigma) {
         if (h->keep) (void)hipFree(h->keep);
@@ -1168,6 +1216,8 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     if (h->D == 2 && comp != 2) return LBEM_EINVAL;
     if (m > 0 && (!cells || !weight)) return LBEM_EINVAL;
     if (!h->have_medium) return LBEM_ESTATE;
+    API_SHARED;
+    HIP_OK(follow_ticks(h));
     if (hipStreamSynchronize(h->stream) != hipSuccess) return LBEM_EDEVICE;
     free_source(h);
     if (m == 0) return LBEM_OK;
@@ -1269,6 +1319,7 @@ int lbem_step(lbem_t h, int64_t nsteps, const double* amp)
 {
     if (!h || nsteps < 0) return LBEM_EINVAL;
     if (!h->have_fields) return LBEM_ESTATE;
+    HIP_OK(follow_ticks(h));
     const bool fuse = fused_ok(h);
     int64_t k = 0;
     while (k < nsteps) {
@@ -1290,6 +1341,7 @@ int lbem_moments(lbem_t h, double* E, double* B, int on_device)
 {
     if (!h) return LBEM_EINVAL;
     if (!h->have_fields) return LBEM_ESTATE;
+    HIP_OK(follow_ticks(h));
     const size_t bytes = (size_t)3 * h->n * 8;
     if (on_device) {
         if (h->impl->fields(h, E, B, nullptr) != hipSuccess) return LBEM_EDEVICE;
@@ -1312,6 +1364,7 @@ int lbem_energy(lbem_t h, double out[4])
 {
     if (!h || !out) return LBEM_EINVAL;
     if (!h->have_fields) return LBEM_ESTATE;
+    HIP_OK(follow_ticks(h));
     double* res = h->partials + (size_t)h->nb_diag * 4;
     HIP_OK(h->impl->fields(h, nullptr, h->scratch, h->partials));
     Geo1 g = geo1(h);
@@ -1360,6 +1413,7 @@ int lbem_get_state(lbem_t h, void* buf, size_t bytes, int on_device)
 {
     if (!h || !buf || bytes < lbem_state_bytes(h)) return LBEM_EINVAL;
     if (!h->have_fields) return LBEM_ESTATE;
+    HIP_OK(follow_ticks(h));
     char hdr[STATE_HDR] = {0};
     StateHeader sh{};
     std::memcpy(sh.magic, STATE_MAGIC, 8);
@@ -1392,6 +1446,7 @@ int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
 {
     if (!h || !buf || bytes < lbem_state_bytes(h)) return LBEM_EINVAL;
     if (!h->have_medium) return LBEM_ESTATE;
+    HIP_OK(follow_ticks(h));
     const char* in = (const char*)buf;
     StateHeader sh{};
     if (on_device) {
@@ -1442,12 +1497,12 @@ struct lbem_batch_s {
     char* pinned[2];
     hipEvent_t ev[2];
     int ring;
-    // graphs cached by the mask of non-empty classes
-    std::vector<std::pair<unsigned, hipGraphExec_t>> graphs;
-    std::vector<hipGraph_t> raw;
+    // one graph per class: ksteps launches of that class's kernel, captured
+    // and instantiated once, in lbem_batch_create
+    hipGraph_t graph[NCLASS];
+    hipGraphExec_t exec[NCLASS];
     int use_graph;
     int blocks;                // persistent grid of each class launch
-    hipEvent_t tick_ev;        // end of the last enqueued tick
 };
 
 static void launch_class(lbem_batch_s* b, int c, int k)
@@ -1468,35 +1523,56 @@ static void launch_class(lbem_batch_s* b, int c, int k)
     }
 }
 
-static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
+// Capture the per-class graphs.  Done once, at creation, with the library
+// lock held exclusively: no graph is ever captured or instantiated while
+// other threads allocate, free or launch through this library.
+static bool capture_classes(lbem_batch_s* b)
 {
-    if (b->use_graph) {
-        for (auto& e : b->graphs)
-            if (e.first == mask) return hipGraphLaunch(e.second, b->stream);
+    std::unique_lock<std::shared_mutex> lk(g_api_mu);
+    for (int c = 0; c < NCLASS; ++c) {
         hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int k = 0; k < b->ksteps; ++k)
-                for (int c = 0; c < NCLASS; ++c)
-                    if (mask & (1u << c)) launch_class(b, c, k);
+            for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k);
             e = hipStreamEndCapture(b->stream, &graph);
         }
-        hipGraphExec_t exec = nullptr;
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             (void)hipGetLastError();
-            b->use_graph = 0;  // fall back to direct launches of the same kernels
+            return false;
+        }
+        b->graph[c] = graph;
+        b->exec[c] = exec;
+    }
+    return true;
+}
+
+static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
+{
+    for (int c = 0; c < NCLASS; ++c) {
+        if (!(mask & (1u << c))) continue;
+        if (b->use_graph) {
+            const hipError_t e = hipGraphLaunch(b->exec[c], b->stream);
+            if (e != hipSuccess) return e;
         } else {
-            b->graphs.push_back({mask, exec});
-            b->raw.push_back(graph);
-            return hipGraphLaunch(exec, b->stream);
+            for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
     }
-    for (int k = 0; k < b->ksteps; ++k)
-        for (int c = 0; c < NCLASS; ++c)
-            if (mask & (1u << c)) launch_class(b, c, k);
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+static void release_graphs(lbem_batch_s* b)
+{
+    for (int c = 0; c < NCLASS; ++c) {
+        if (b->exec[c]) (void)hipGraphExecDestroy(b->exec[c]);
+        if (b->graph[c]) (void)hipGraphDestroy(b->graph[c]);
+        b->exec[c] = nullptr;
+        b->graph[c] = nullptr;
+    }
 }
 
 extern "C" {
@@ -1519,13 +1595,23 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     b->dev = nullptr;
     b->pinned[0] = b->pinned[1] = nullptr;
     b->ev[0] = b->ev[1] = nullptr;
-    b->tick_ev = nullptr;
-    bool ok = hipMalloc((void**)&b->dev, bytes) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&b->pinned[0], bytes, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&b->pinned[1], bytes, hipHostMallocDefault) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&b->tick_ev, hipEventDisableTiming) == hipSuccess;
+    for (int c = 0; c < NCLASS; ++c) {
+        b->graph[c] = nullptr;
+        b->exec[c] = nullptr;
+    }
+    bool ok;
+    {
+        API_SHARED;
+        ok = hipMalloc((void**)&b->dev, bytes) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&b->pinned[0], bytes, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&b->pinned[1], bytes, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming) == hipSuccess;
+    }
+    if (ok && b->use_graph && !capture_classes(b)) {
+        release_graphs(b);
+        b->use_graph = 0;  // direct launches of the same kernels
+    }
     if (ok) {
         std::memset(b->pinned[0], 0, bytes);
         std::memset(b->pinned[1], 0, bytes);
@@ -1543,14 +1629,13 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
 int lbem_batch_destroy(lbem_batch_t b)
 {
     if (!b) return LBEM_OK;
+    API_SHARED;
     (void)hipStreamSynchronize(b->stream);
-    for (auto& e : b->graphs) (void)hipGraphExecDestroy(e.second);
-    for (auto g : b->raw) (void)hipGraphDestroy(g);
+    release_graphs(b);
     for (int i = 0; i < 2; ++i) {
         if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
         if (b->pinned[i]) (void)hipHostFree(b->pinned[i]);
     }
-    if (b->tick_ev) (void)hipEventDestroy(b->tick_ev);
     if (b->dev) (void)hipFree(b->dev);
     delete b;
     return LBEM_OK;
@@ -1631,12 +1716,13 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
     if (hipEventRecord(b->ev[b->ring], b->stream) != hipSuccess) return LBEM_EDEVICE;
     b->ring ^= 1;
     if (mask && enqueue_tick(b, mask) != hipSuccess) return LBEM_EDEVICE;
-    // ... and later work on a member's own stream (moments, destroy) follows it
-    if (hipEventRecord(b->tick_ev, b->stream) != hipSuccess) return LBEM_EDEVICE;
+    // ... and later work on a member's own stream (moments, destroy) follows
+    // it: the member's stream waits on this event at its next use (follow_ticks)
     for (int i = 0; i < count; ++i) {
         lbem_s* h = handles[i];
         if (nsteps[i] == 0 || h->stream == b->stream) continue;
-        if (hipStreamWaitEvent(h->stream, b->tick_ev, 0) != hipSuccess) return LBEM_EDEVICE;
+        if (hipEventRecord(h->tick_ev, b->stream) != hipSuccess) return LBEM_EDEVICE;
+        h->tick_pending = true;
     }
     for (int i = 0; i < count; ++i) {
         lbem_s* h = handles[i];

@@ -110,4 +110,4 @@ def test_config4_full_512_deviation_storage(prec):
     p = inputs.config4(nsteps=k)
     announce(f"config4 512^3 {prec} full size")
     samples = [(256, 256, 256), (255, 258, 250), (511, 0, 300)]
-    sampled_parity(p, prec, k, samples, 2e-3)
+    sampled_parity(p, prec, k, samples, 1e-3)

@@ -90,4 +90,4 @@ def test_3d_2pow30_cells_ghost_zmarch():
     p = inputs.Problem(dim=3, shape=shape, eps_r=cheap_medium(shape), mu_r=None, E0=E, B0=B, nsteps=3,
                        name="3d-1024")
     samples = [(10, 12, 14), (1021, 1020, 1023), (0, 1023, 1023), (513, 701, 899)]
-    sampled(p, "f16ghost", 3, samples, 2e-3)
+    sampled(p, "f16ghost", 3, samples, 1e-3)

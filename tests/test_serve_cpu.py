@@ -157,3 +157,69 @@ def test_requests_joining_mid_flight_overlap():
     Scheduler(ex, budget_bytes=10**9, max_slots=8, steps_per_tick=50).run([long, late])
     assert max(shared) == 2
     assert late.t_done < long.t_done
+
+
+class _Pending:
+    """A worker-thread future that completes at a virtual time."""
+
+    def __init__(self, ex, t_ready, value):
+        self.ex, self.t_ready, self.value = ex, t_ready, value
+
+    def done(self):
+        return self.ex.t >= self.t_ready
+
+
+class WorkerExecutor(FakeExecutor):
+    """Set-up and read-back take virtual time on worker threads.  A tick may
+    only name lattices whose set-up has completed and whose read-back has not
+    been issued: the library's handles are not shared between a worker call
+    and a batch tick."""
+
+    def __init__(self, setup_s=2e-3, finish_s=1e-3, **kw):
+        super().__init__(setup_s=0.0, **kw)
+        self.setup_dt, self.finish_dt = setup_s, finish_s
+        self.busy = set()        # slots a worker is still setting up or reading back
+        self.pending = []
+
+    def admit(self, r):
+        f = super().admit(r)
+        self.busy.add(f.slot)
+        fut = _Pending(self, self.t + self.setup_dt, f.slot)
+        self.pending.append(fut)
+        return fut
+
+    def ready(self, f):
+        if f.done() and getattr(f, "value", None) in self.busy and f in self.pending:
+            self.busy.discard(f.value)     # the worker finished the set-up
+            self.pending.remove(f)
+        return f.done()
+
+    def result(self, f):
+        assert f.done()
+        self.ready(f)
+        return f.value
+
+    def wait_any(self, futs):
+        ts = [f.t_ready for f in futs if not f.done()]
+        if ts:
+            self.t = max(self.t, min(ts))
+
+    def tick(self, slots, nsteps):
+        assert not (set(slots) & self.busy), "a tick names a lattice owned by a worker"
+        super().tick(slots, nsteps)
+
+    def finish_async(self, slot, want=True):
+        assert slot not in self.busy
+        f = super().finish_async(slot, want)
+        return _Pending(self, self.t + self.finish_dt, f.slot)
+
+
+def test_ticks_never_touch_lattices_owned_by_workers():
+    ex = WorkerExecutor(rate=5e8)
+    reqs = mix(120, rate=400.0, seed=9)
+    rep = Scheduler(ex, budget_bytes=20_000_000, max_slots=12, steps_per_tick=40).run(reqs)
+    assert rep.completed + rep.rejected == len(reqs)
+    got = {rid: steps for rid, steps, want in ex.finished}
+    for r in reqs:
+        if r.status == "done":
+            assert got[r.rid] == r.nsteps
