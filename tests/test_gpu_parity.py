@@ -8,6 +8,14 @@ non-compliant in the header.  The energy-norm error
 sqrt(sum eps_abs|dE|^2 + |dB|^2/mu) / sqrt(sum eps_abs|E|^2 + |B|^2/mu) is
 reported beside them.
 
+A field's relative error is ill-conditioned when the field passes through a
+temporal node: in the 32^3 sphere crop at step 300 E holds 0.67 % of the EM
+energy (|E| = 0.59 against 5 - 7 at the neighbouring checkpoints; the oracle
+shows it on the CPU), and its relative L2 is then ten times the energy-norm
+error.  The bar therefore applies to each field that holds at least
+FIELD_SHARE_MIN of the EM energy at the checkpoint, and the energy-norm error
+is held to the bar always; a field below the share is reported, not asserted.
+
 White-noise fields (random_problem) are as far from equilibrium as a state can
 be: the 16-bit codes then carry O(1) of each population, rounded to relative
 precision u per store (u = 2^-11 FP16, 2^-8 BF16).  Those code-path tests use
@@ -30,6 +38,30 @@ BF16_BAND = 5e-3
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "bf16dev": BF16_BAND, "f16ghost": 1e-3,
        "bf16ghost": BF16_BAND}
 LOWP = ["f16dev", "bf16dev", "f16ghost", "bf16ghost"]
+
+
+FIELD_SHARE_MIN = 0.05
+
+
+def field_shares(Eo, Bo, o, mu=None):
+    """Fractions of the oracle's EM energy held by E and by B."""
+    ea = o.medium()["eps_abs"]
+    m = 1.0 if mu is None else mu
+    eE = float(np.sum(ea * (Eo ** 2).sum(0)))
+    eB = float(np.sum((Bo ** 2).sum(0) / m))
+    tot = eE + eB
+    return (eE / tot, eB / tot) if tot > 0 else (1.0, 1.0)
+
+
+def check_fields(eE, eB, eN, shares, t):
+    """The bar on each field with a share of the energy >= FIELD_SHARE_MIN, and
+    on the energy norm."""
+    if shares[0] < FIELD_SHARE_MIN or shares[1] < FIELD_SHARE_MIN:
+        announce(f"  field energy shares E {shares[0]:.4f} B {shares[1]:.4f}: "
+                 f"a field below {FIELD_SHARE_MIN} is reported, not asserted")
+    assert eN <= t, (eE, eB, eN)
+    assert shares[0] < FIELD_SHARE_MIN or eE <= t, (eE, eB, eN, shares)
+    assert shares[1] < FIELD_SHARE_MIN or eB <= t, (eE, eB, eN, shares)
 
 
 def white_noise_bar(prec, steps):
@@ -56,7 +88,7 @@ def compare(p, nsteps, prec, streaming="auto", tau=None, env=None, tol=None):
     eN = energy_norm_error(Eg, Bg, Eo, Bo, o, p.mu_r)
     announce(f"  rel L2 E={eE:.3e} B={eB:.3e} energy-norm={eN:.3e}")
     t = TOL[prec] if tol is None else tol
-    assert eE <= t and eB <= t, (eE, eB, eN)
+    check_fields(eE, eB, eN, field_shares(Eo, Bo, o, p.mu_r), t)
     assert s.t == nsteps
     return s, o
 
@@ -307,8 +339,24 @@ def test_deviation_storage_config1(prec):
 
 @pytest.mark.parametrize("prec", LOWP)
 def test_deviation_storage_3d_crop(prec):
-    p = inputs.config3(nsteps=300, crop_n=32)
-    compare(p, 300, prec)
+    """32^3 sphere crop with the dipole, three checkpoints: E sits at a
+    temporal node at step 300 (0.67 % of the energy) and is asserted at 260
+    and 340."""
+    p = inputs.config3(nsteps=340, crop_n=32)
+    s = gpu_run(p, 0, prec)
+    o = oracle_run(p, 0)
+    t = 0
+    for k in (260, 300, 340):
+        s.step(k - t, p.amp[t:k])
+        o.step(k - t, p.amp[t:k])
+        t = k
+        (Eg, Bg), (Eo, Bo) = s.moments(), o.fields()
+        eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+        eN = energy_norm_error(Eg, Bg, Eo, Bo, o)
+        sh = field_shares(Eo, Bo, o)
+        announce(f"{p.name} {prec} {k} steps: rel L2 E={eE:.3e} B={eB:.3e} energy-norm={eN:.3e} "
+                 f"shares E {sh[0]:.4f} B {sh[1]:.4f}")
+        check_fields(eE, eB, eN, sh, TOL[prec])
 
 
 @pytest.mark.parametrize("prec", LOWP)
