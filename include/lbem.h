@@ -47,7 +47,9 @@ typedef enum {
     LBEM_EUNSTABLE = -3,  /* medium gives a rest weight w0(x) outside [0,1)       */
     LBEM_ENONFINITE = -4, /* a diagnostic sum is NaN or Inf                       */
     LBEM_EDEVICE = -5,    /* HIP runtime error (no device, launch failure, ...)   */
-    LBEM_ESTATE = -6      /* call out of order (e.g. step before init_fields)     */
+    LBEM_ESTATE = -6,     /* call out of order (e.g. step before init_fields)     */
+    LBEM_ETOOBIG = -7     /* lattice exceeds a fixed static buffer
+                             (lbem_energy_noalloc)                               */
 } lbem_status;
 
 /* Storage / arithmetic formats of the populations. */
@@ -172,6 +174,19 @@ int lbem_moments(lbem_t h, double* E, double* B, int on_device);
  *   out[3]  sum_x |B|^2
  * ENONFINITE if any of them is NaN or Inf (the values are still written). */
 int lbem_energy(lbem_t h, double out[4]);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * diagnostics as lbem_energy, bit for bit, with the FP64 B field and the
+ * reduction partials in a static device array of the library (64 MiB per GPU,
+ * held until the process ends) instead of the handle's scratch.  The call
+ * allocates and frees nothing.  Lattices above LBEM_NOALLOC_MAX_CELLS cells
+ * return LBEM_ETOOBIG before any work is enqueued.  All calls on one GPU share
+ * the array: calls that overlap in time on the same GPU (from two threads, or
+ * on two streams without an ordering between them) race and give undefined
+ * results.  Synchronises the handle's stream; other errors as lbem_energy. */
+#define LBEM_NOALLOC_MAX_CELLS 2781712   /* 3n + 4 ceil(n/256) + 4 doubles <= 64 MiB */
+int lbem_energy_noalloc(lbem_t h, double out[4]);
 
 /* Completed steps since lbem_init_fields (-1 for an invalid handle). */
 int64_t lbem_time(lbem_t h);

@@ -711,6 +711,52 @@ static int tile_id(const Geo& g, int tx, int ty, int z)
 }
 
 // ---------------------------------------------------------------------------
+// static device scratch of lbem_energy_noalloc
+// ---------------------------------------------------------------------------
+// The FP64 B field (3n doubles) read by the divergence stencil and the
+// per-block partial sums (4 per block + 4 results) live in this array instead
+// of the handle's scratch.  Every GPU the library runs on holds its own copy
+// until the process ends; every call on that GPU shares it and leaves the
+// last call's contents.  The kernels write every element they later read, so
+// nothing needs clearing between calls.
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_BYTES / sizeof(double);
+static __device__ __align__(256) double noalloc_scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES];   // device address of the array, per device
+
+constexpr size_t noalloc_doubles(int64_t n) { return (size_t)3 * n + (size_t)((n + NT - 1) / NT) * 4 + 4; }
+static_assert(noalloc_doubles(LBEM_NOALLOC_MAX_CELLS) <= NOALLOC_DOUBLES &&
+                  noalloc_doubles(LBEM_NOALLOC_MAX_CELLS + 1) > NOALLOC_DOUBLES,
+              "LBEM_NOALLOC_MAX_CELLS is the largest lattice the static scratch holds");
+
+// Device address of noalloc_scratch on `device`, looked up once per device
+// with that device current (host code never passes the symbol itself).
+hipError_t noalloc_address(int device, double** out)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[device] = (double*)p;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -731,6 +777,8 @@ const char* lbem_strerror(int code)
         case LBEM_ENONFINITE: return "non-finite diagnostic (NaN or Inf)";
         case LBEM_EDEVICE: return "HIP device or launch error";
         case LBEM_ESTATE: return "call out of order";
+        case LBEM_ETOOBIG:
+            return "lattice too large for the static scratch of lbem_energy_noalloc (see LBEM_NOALLOC_MAX_CELLS)";
         default: return "unknown status";
     }
 }
@@ -1374,6 +1422,34 @@ int lbem_energy(lbem_t h, double out[4])
         hipLaunchKernelGGL((k_divb<3>), dim3(h->nb_diag), dim3(NT), 0, h->stream, h->scratch, g, h->partials);
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(NT), 0, h->stream, h->partials, h->nb_diag, res);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(out[k])) return LBEM_ENONFINITE;
+    return LBEM_OK;
+}
+
+// lbem_energy with its scratch in the static device array: no allocation.
+int lbem_energy_noalloc(lbem_t h, double out[4])
+{
+    if (!h || !out) return LBEM_EINVAL;
+    if (!h->have_fields) return LBEM_ESTATE;
+    if (h->n > LBEM_NOALLOC_MAX_CELLS) return LBEM_ETOOBIG;
+    double* base = nullptr;
+    HIP_OK(noalloc_address(h->device, &base));
+    HIP_OK(follow_ticks(h));
+    double* bfield = base;                          // [3][n]
+    double* partials = base + (size_t)3 * h->n;     // [nb_diag][4], then the 4 results
+    double* res = partials + (size_t)h->nb_diag * 4;
+    HIP_OK(h->impl->fields(h, nullptr, bfield, partials));
+    Geo1 g = geo1(h);
+    if (h->D == 2)
+        hipLaunchKernelGGL((k_divb<2>), dim3(h->nb_diag), dim3(NT), 0, h->stream, bfield, g, partials);
+    else
+        hipLaunchKernelGGL((k_divb<3>), dim3(h->nb_diag), dim3(NT), 0, h->stream, bfield, g, partials);
+    HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(NT), 0, h->stream, partials, h->nb_diag, res);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "_build", "liblbem.so")
 
 LBEM_OK, LBEM_EINVAL, LBEM_ENOMEM, LBEM_EUNSTABLE, LBEM_ENONFINITE, LBEM_EDEVICE, LBEM_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
+LBEM_ETOOBIG = -7
+NOALLOC_MAX_CELLS = 2781712      # LBEM_NOALLOC_MAX_CELLS of include/lbem.h
 PREC = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3, "f16ghost": 4, "bf16ghost": 5, "f16": 6}
 STREAMING = {"auto": 0, "pull": 1, "aa": 2}
 
@@ -25,7 +27,8 @@ SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_mediu
            "lbem_init_fields", "lbem_set_source", "lbem_step", "lbem_moments", "lbem_energy",
            "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
            "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state",
-           "lbem_set_boundary", "lbem_set_absorber", "lbem_set_dispersion", "lbem_set_anisotropy")
+           "lbem_set_boundary", "lbem_set_absorber", "lbem_set_dispersion", "lbem_set_anisotropy",
+           "lbem_energy_noalloc")
 BOUNDARY = {"periodic": 0, "pec": 1, "pmc": 2}
 
 
@@ -65,6 +68,7 @@ def load():
     L.lbem_step.argtypes = [vp, i64, vp]
     L.lbem_moments.argtypes = [vp, vp, vp, C.c_int]
     L.lbem_energy.argtypes = [vp, dp]
+    L.lbem_energy_noalloc.argtypes = [vp, dp]
     L.lbem_time.argtypes = [vp]
     L.lbem_time.restype = i64
     L.lbem_steps_per_launch.argtypes = [vp]
@@ -249,6 +253,15 @@ class Solver:
         rc = load().lbem_energy(self._h, out.ctypes.data_as(C.POINTER(C.c_double)))
         if check:
             self._chk(rc, "lbem_energy")
+        return dict(energy=out[0], qc=out[1], divb2=out[2], b2=out[3], status=rc)
+
+    def energy_noalloc(self, check=True) -> dict:
+        """lbem_energy_noalloc: the same diagnostics with the library's static
+        device scratch (no allocation; lattices up to NOALLOC_MAX_CELLS)."""
+        out = np.zeros(4)
+        rc = load().lbem_energy_noalloc(self._h, out.ctypes.data_as(C.POINTER(C.c_double)))
+        if check:
+            self._chk(rc, "lbem_energy_noalloc")
         return dict(energy=out[0], qc=out[1], divb2=out[2], b2=out[3], status=rc)
 
     # -- checkpoint / resume -------------------------------------------------

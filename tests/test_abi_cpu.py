@@ -88,3 +88,14 @@ def test_null_handle_calls():
     assert L.lbem_state_bytes(None) == 0
     assert L.lbem_get_state(None, None, 0, 0) == lbem.LBEM_EINVAL
     assert L.lbem_set_state(None, None, 0, 0) == lbem.LBEM_EINVAL
+    assert L.lbem_energy_noalloc(None, None) == lbem.LBEM_EINVAL
+    assert "static scratch" in lbem.strerror(lbem.LBEM_ETOOBIG)
+
+
+def test_noalloc_limit_matches_header():
+    src = open(os.path.join(ROOT, "include", "lbem.h")).read()
+    m = re.search(r"#define LBEM_NOALLOC_MAX_CELLS (\d+)", src)
+    assert m and int(m.group(1)) == lbem.NOALLOC_MAX_CELLS
+    n = lbem.NOALLOC_MAX_CELLS
+    need = lambda k: 3 * k + 4 * (-(-k // 256)) + 4      # doubles: B field, partials, results
+    assert need(n) * 8 <= 64 << 20 < need(n + 1) * 8
