@@ -1347,6 +1347,278 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
 }
 
 // ---------------------------------------------------------------------------
+// 3D deviation storage, row tiles: every stored cell decoded once
+// ---------------------------------------------------------------------------
+// A block of NTB threads owns `ty` whole x-rows (y0 .. y0+rows-1) of a chunk
+// of `lz` planes and marches along z.  A thread owns up to CX cells of one row
+// (x = q + k*tpr).  Per plane it reads its cells' stored moments and 16-bit
+// codes once, with aligned loads, and decodes every outgoing population (rest
+// and dropped ghost entries included) in FP32; the +-x and +-y ones go to LDS
+// for the in-plane neighbours, the +-z and rest ones stay in registers for
+// the planes the march visits next.  The rows y0-1 and y0+rows are decoded
+// only for the +y / -y populations that enter the tile.  The update of plane
+// z then pulls every population from LDS or registers.  The decoding and the
+// collision are those of k_step_dev, so the two agree bit for bit.
+constexpr int NTR = 1024;        // largest block
+constexpr int ROWX_MAX = 1024;   // longest row
+
+struct RowGeo {
+    int nx, ny, nz;
+    int tpr, ty;          // threads per row (multiple of 64, CX*tpr >= nx), rows per tile (NTB / tpr)
+    int tiles_y, lz, nblocks, xcd;
+    int64_t n;
+};
+
+// in-plane velocities of the LDS exchange: j = 0 +x, 1 +y, 2 -x, 3 -y
+__host__ __device__ constexpr int inplane_vel(int j) { return j == 0 ? 1 : (j == 1 ? 2 : (j == 2 ? 4 : 5)); }
+
+// population (i,p) of a cell from its stored moments Mv, scale sc and codes
+// (get), exactly as dev_load forms it
+template <bool GH, class Get>
+__device__ __forceinline__ float row_pop(const float (&Mv)[6], const Get& get, float sc, float wc0, int i, int p)
+{
+    constexpr int D = 3, P = 3;
+    float Lam[P], Bb[D];
+#pragma unroll
+    for (int t = 0; t < P; ++t) Lam[t] = (t == p) ? Mv[t] : 0.f;
+    const int a = pair_a(D, p), bq = pair_b(D, p);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        const bool need = i != 0 && ((e == bq && cvel(D, i, a) != 0) || (e == a && cvel(D, i, bq) != 0));
+        Bb[e] = need ? Mv[P + e] : 0.f;
+    }
+    const float g0 = dev_eq<D>(i, p, Lam, Bb, wc0);
+    return g0 + dev_value_of<D, GH>(get, i, p, sc, wc0);
+}
+
+__device__ __forceinline__ float row_scale(const float (&Mv)[6])
+{
+    float m = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) m = fmaxf(m, fabsf(Mv[t]));
+    float s, inv;
+    pow2_scale(m, s, inv);
+    return s;
+}
+
+// populations (i, p = 0..2) of velocity i of cell c, reading only the
+// moments and codes they need (halo rows, first and last plane of a chunk)
+template <typename H, bool GH>
+__device__ __forceinline__ void row_pops_of(const float* Min, const H* Din, int64_t n, int64_t c, int i,
+                                            float (&out)[3])
+{
+    float Mv[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) Mv[t] = Min[(int64_t)t * n + c];
+    const float sc = row_scale(Mv);
+    auto get = [&](int sl) { return h2f<H>(Din[(int64_t)sl * n + c]); };
+#pragma unroll
+    for (int p = 0; p < 3; ++p) out[p] = row_pop<GH>(Mv, get, sc, 0.f, i, p);
+}
+
+// NTS: streaming stores of the state.  src_*: per (block, plane of the chunk)
+// a range [off[b*lz + rel], off[b*lz + rel + 1]) of (row*nx + x, pair) entries
+// with their value per unit amplitude.
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
+__global__ __launch_bounds__(NTB) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
+                                                   const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                                   const RowGeo g, const int* __restrict__ soff,
+                                                   const int2* __restrict__ sent, const float* __restrict__ sval,
+                                                   const float amp, const float omega, const int tau_half)
+{
+    constexpr int D = 3, Q = 7, P = 3, NM = P + D, NC = DevSlots<D, GH>::N;
+    constexpr int ROWC_MAX = CX * NTB;       // cells of one plane of the tile (ty * nx <= CX * NTB)
+    constexpr int RX = CX * NTB < ROWX_MAX ? CX * NTB : ROWX_MAX;   // longest row of this block size
+    __shared__ float lp[12 * ROWC_MAX];      // [j*3 + p][row*nx + x]: in-plane outgoing populations
+    __shared__ float lh[6 * RX];             // [side*3 + p][x]: +y of row y0-1 (side 0), -y of row y0+rows (side 1)
+
+    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
+    const int tyi = b % g.tiles_y, zc = b / g.tiles_y;
+    const int y0 = tyi * g.ty, z0 = zc * g.lz;
+    const int z1 = min(z0 + g.lz, g.nz);
+    const int rows = min(g.ty, g.ny - y0);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t n = g.n, nxy = (int64_t)nx * ny;
+    const int r = threadIdx.x / g.tpr, q = threadIdx.x % g.tpr;
+    const bool row_ok = r < rows;
+    const int y = y0 + r;
+    const int yh0 = (y0 - 1 + ny) % ny, yh1 = (y0 + rows) % ny;
+    const bool has_src = soff != nullptr;
+
+    int xs[CX];
+    bool ok[CX];
+#pragma unroll
+    for (int k = 0; k < CX; ++k) {
+        xs[k] = q + k * g.tpr;
+        ok[k] = row_ok && xs[k] < nx;
+    }
+    auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+
+    float pz_prev[CX][P], pz_cur[CX][P], rest_cur[CX][P], cl2_cur[CX];
+    float mz_new[CX][P], pz_next[CX][P], rest_next[CX][P], cl2_next[CX];
+
+    // decode plane zz of the own cells: in-plane populations to LDS (if
+    // to_lds), -z to mz, +z to pz, rest to rs
+    auto decode_plane = [&](int zz, bool to_lds, float (&mz)[CX][P], float (&pz)[CX][P], float (&rs)[CX][P],
+                            float (&cl)[CX]) {
+        const int64_t zo = (int64_t)zz * nxy + (int64_t)y * nx;
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            const int64_t c = zo + xs[k];
+            float Mv[NM], cd[NC];
+#pragma unroll
+            for (int t = 0; t < NM; ++t) Mv[t] = Min[(int64_t)t * n + c];
+#pragma unroll
+            for (int sl = 0; sl < NC; ++sl) cd[sl] = h2f<H>(Din[(int64_t)sl * n + c]);
+            const float cl2 = cl2a[c];
+            const float wc0 = 1.f / cl2 - float(D);
+            cl[k] = cl2;
+            const float sc = row_scale(Mv);
+            auto get = [&](int sl) { return cd[sl]; };
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                rs[k][p] = row_pop<GH>(Mv, get, sc, wc0, 0, p);
+                pz[k][p] = row_pop<GH>(Mv, get, sc, wc0, 3, p);
+                mz[k][p] = row_pop<GH>(Mv, get, sc, wc0, 6, p);
+            }
+            if (to_lds) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        lp[(j * 3 + p) * ROWC_MAX + r * nx + xs[k]] =
+                            row_pop<GH>(Mv, get, sc, wc0, inplane_vel(j), p);
+            }
+        }
+    };
+    // the +y populations of row y0-1 and the -y ones of row y0+rows, plane zz
+    auto decode_halo = [&](int zz) {
+        for (int t = threadIdx.x; t < 2 * nx; t += NTB) {
+            const int side = t >= nx, x = t - side * nx;
+            const int64_t c = (int64_t)zz * nxy + (int64_t)(side ? yh1 : yh0) * nx + x;
+            float o[3];
+            row_pops_of<H, GH>(Min, Din, n, c, side ? 5 : 2, o);
+#pragma unroll
+            for (int p = 0; p < P; ++p) lh[(side * 3 + p) * RX + x] = o[p];
+        }
+    };
+
+    // prologue: +z populations of plane z0-1, all of plane z0
+    {
+        const int zm = wrapz(z0 - 1);
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            float o[3];
+            row_pops_of<H, GH>(Min, Din, n, (int64_t)zm * nxy + (int64_t)y * nx + xs[k], 3, o);
+#pragma unroll
+            for (int p = 0; p < P; ++p) pz_prev[k][p] = o[p];
+        }
+        decode_plane(z0, true, mz_new, pz_cur, rest_cur, cl2_cur);
+        decode_halo(z0);
+    }
+    __syncthreads();
+
+    for (int z = z0; z < z1; ++z) {
+        // in-plane arrivals of plane z
+        float arr[CX][4][P];
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            const int x = xs[k];
+            const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+            const int rc = r * nx;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                arr[k][0][p] = lp[(0 * 3 + p) * ROWC_MAX + rc + xm];                       // +x from x-1
+                arr[k][2][p] = lp[(2 * 3 + p) * ROWC_MAX + rc + xp];                       // -x from x+1
+                arr[k][1][p] = r > 0 ? lp[(1 * 3 + p) * ROWC_MAX + rc - nx + x]            // +y from y-1
+                                     : lh[(0 * 3 + p) * RX + x];
+                arr[k][3][p] = r < rows - 1 ? lp[(3 * 3 + p) * ROWC_MAX + rc + nx + x]     // -y from y+1
+                                            : lh[(1 * 3 + p) * RX + x];
+            }
+        }
+        __syncthreads();
+        // plane z+1: all of it while the march continues, else only its -z populations
+        const int zn = wrapz(z + 1);
+        if (z + 1 < z1) {
+            decode_plane(zn, true, mz_new, pz_next, rest_next, cl2_next);
+            decode_halo(zn);
+        } else {
+#pragma unroll
+            for (int k = 0; k < CX; ++k) {
+                if (!ok[k]) continue;
+                float o[3];
+                row_pops_of<H, GH>(Min, Din, n, (int64_t)zn * nxy + (int64_t)y * nx + xs[k], 6, o);
+#pragma unroll
+                for (int p = 0; p < P; ++p) mz_new[k][p] = o[p];
+            }
+        }
+        // update plane z
+        int s0 = 0, s1 = 0;
+        if (has_src) {
+            s0 = soff[b * g.lz + (z - z0)];
+            s1 = soff[b * g.lz + (z - z0) + 1];
+        }
+        const bool any_src = s1 > s0 || MU;
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            const int x = xs[k];
+            const int64_t c = (int64_t)z * nxy + (int64_t)y * nx + x;
+            float f[Q][P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                f[0][p] = rest_cur[k][p];
+                f[1][p] = arr[k][0][p];
+                f[2][p] = arr[k][1][p];
+                f[3][p] = pz_prev[k][p];
+                f[4][p] = arr[k][2][p];
+                f[5][p] = arr[k][3][p];
+                f[6][p] = mz_new[k][p];
+            }
+            const float cl2 = cl2_cur[k];
+            const float wc0 = 1.f / cl2 - float(D);
+            float rho[P], K[D], Sp[P];
+            moments<D, float>(f, rho, K);
+#pragma unroll
+            for (int p = 0; p < P; ++p) Sp[p] = 0.f;
+            const int loc = r * nx + x;
+            for (int e = s0; e < s1; ++e) {
+                const int2 en = sent[e];
+                if (en.x == loc) {
+                    const float v = sval[e] * amp;
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        if (en.y == p) Sp[p] = v;
+                }
+            }
+            if (MU) {
+                float dl[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * n + c];
+                add_mu_source<D, float>(K, cl2, dl, Sp);
+            }
+            dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, n, (int)c,
+                                             Mout, Dout);
+        }
+        // the march moves on one plane
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            cl2_cur[k] = cl2_next[k];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                pz_prev[k][p] = pz_cur[k][p];
+                pz_cur[k][p] = pz_next[k][p];
+                rest_cur[k][p] = rest_next[k][p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3D deviation storage, two steps per launch (temporal blocking)
 // ---------------------------------------------------------------------------
 // The column tiling, z-march and LDS buffers of k_step_fused3d, on the 16-bit

@@ -152,6 +152,13 @@ struct lbem_s {
     int2* zsrc_ent;
     void* zsrc_val;
     int64_t nzsrc;
+    // 3D deviation kernel on whole-row tiles (k_step_dev3r), marching along z
+    int rowk;
+    RowGeo rgeo;
+    int* rsrc_off;
+    int2* rsrc_ent;
+    float* rsrc_val;
+    int64_t nrsrc;
     // state
     // non-periodic faces and absorbing layer
     int bc_kind[3];
@@ -470,10 +477,44 @@ struct DevImpl : Impl {
         const int P = Lat<D>::P;
         return (H*)(h->pop[k] + align256((size_t)(P + D) * h->n * 4));
     }
+    template <bool MU, bool NTS, int NTB>
+    static void go_row_n(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
+    {
+        hipLaunchKernelGGL((k_step_dev3r<H, GH, MU, NTS, 2, NTB>), dim3(h->rgeo.nblocks), dim3(NTB), 0, h->stream,
+                           M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                           (const float*)h->dlnmu, h->rgeo, so, h->rsrc_ent, h->rsrc_val, amp, om, th);
+    }
+    template <bool MU>
+    static hipError_t go_row(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
+    {
+        if constexpr (D == 3) {
+            const int nb = h->rgeo.tpr * h->rgeo.ty;
+            if (h->nts) {
+                if (nb == 1024) go_row_n<MU, true, 1024>(h, from, to, so, amp, om, th);
+                else if (nb == 512) go_row_n<MU, true, 512>(h, from, to, so, amp, om, th);
+                else go_row_n<MU, true, 256>(h, from, to, so, amp, om, th);
+            } else {
+                if (nb == 1024) go_row_n<MU, false, 1024>(h, from, to, so, amp, om, th);
+                else if (nb == 512) go_row_n<MU, false, 512>(h, from, to, so, amp, om, th);
+                else go_row_n<MU, false, 256>(h, from, to, so, amp, om, th);
+            }
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     template <int RM, int V, bool MU, bool BX = false>
     static hipError_t go(lbem_s* h, int from, int to, float amp)
     {
         SrcArgs<float> s;
+        if constexpr (D == 3 && !BX && RM == R_PULL) {
+            if (h->rowk) {
+                const int* so = h->nrsrc ? h->rsrc_off : nullptr;
+                const float om = (float)(1.0 / h->cfg.tau);
+                const int th = h->cfg.tau == 0.5;
+                return go_row<MU>(h, from, to, so, amp, om, th);
+            }
+        }
         if constexpr (D == 3 && !BX) {
             if (h->zmarch) {
                 s.off = h->nzsrc ? h->zsrc_off : nullptr;
@@ -701,6 +742,34 @@ static void make_zmarch_geo(lbem_s* h)
     g.xcd = env_int("LBEM_DEV3Z_XCD", 0);
 }
 
+// Whole-row tiles of k_step_dev3r: CX = 2 cells per thread, tpr threads per
+// row (a power of two from 64 up to the block size), ty = block/tpr rows per
+// tile; z chunks as long as still give >= 1024 blocks.  Rows longer than
+// twice the block (or ROWX_MAX) keep the column-tile z-march.
+static void make_row_geo(lbem_s* h)
+{
+    const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
+    // 512 threads: two blocks per CU (73 KB of LDS each) hide the memory
+    // latency that one 1024-thread block with taller tiles leaves exposed
+    // (measured at 512^3: 3.20 ms per step against 5.31, 256 threads 3.61)
+    int ntb = env_int("LBEM_DEV3R_NT", 512);
+    if (ntb != 256 && ntb != 1024) ntb = 512;
+    h->rowk = (h->zmarch && nx <= std::min(ROWX_MAX, 2 * ntb)) ? env_int("LBEM_DEV3R", 1) : 0;
+    RowGeo& g = h->rgeo;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
+    int tpr = 64;
+    while (2 * tpr < nx) tpr <<= 1;
+    if (tpr > ntb) tpr = ntb;
+    g.tpr = tpr;
+    g.ty = ntb / tpr;
+    g.tiles_y = (ny + g.ty - 1) / g.ty;
+    int lz = 32;
+    while (lz > 1 && (int64_t)g.tiles_y * ((nz + lz - 1) / lz) < 1024) lz /= 2;
+    g.lz = std::max(1, env_int("LBEM_DEV3R_LZ", lz));
+    g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
+    g.xcd = env_int("LBEM_DEV3R_XCD", 1);
+}
+
 // inverse of tile_coords()
 static int tile_id(const Geo& g, int tx, int ty, int z)
 {
@@ -844,6 +913,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     make_geo(h);
     make_fused_geo(h);
     make_zmarch_geo(h);
+    make_row_geo(h);
     // Measured: streaming loads/stores slow a launch whose state fits the
     // 256 MB Infinity Cache (by up to 1.8x) and speed it up beyond that: in 3D
     // from about 1.5 times the cache on (2-10 %; at 344 MB still 9 % slower),
@@ -884,8 +954,13 @@ static void free_source(lbem_s* h)
     if (h->zsrc_off) (void)hipFree(h->zsrc_off);
     if (h->zsrc_ent) (void)hipFree(h->zsrc_ent);
     if (h->zsrc_val) (void)hipFree(h->zsrc_val);
+    if (h->rsrc_off) (void)hipFree(h->rsrc_off);
+    if (h->rsrc_ent) (void)hipFree(h->rsrc_ent);
+    if (h->rsrc_val) (void)hipFree(h->rsrc_val);
     h->fsrc_off = nullptr; h->fsrc_ent = nullptr; h->fsrc_val = nullptr;
     h->zsrc_off = nullptr; h->zsrc_ent = nullptr; h->zsrc_val = nullptr;
+    h->rsrc_off = nullptr; h->rsrc_ent = nullptr; h->rsrc_val = nullptr;
+    h->nrsrc = 0;
     h->nsrc = 0;
     h->nfsrc = 0;
     h->nzsrc = 0;
@@ -983,6 +1058,45 @@ static int build_zmarch_source(lbem_s* h, const std::vector<std::pair<int64_t, d
     if (e == hipSuccess && ms) e = hipMemcpy(h->zsrc_val, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return LBEM_EDEVICE;
     h->nzsrc = (int64_t)ms;
+    return LBEM_OK;
+}
+
+// Source entries of the whole-row tiling: per (block, plane of its chunk) the
+// cells (row * nx + x) that carry a current, with S per unit amplitude.
+static int build_row_source(lbem_s* h, const std::vector<std::pair<int64_t, double>>& cells, int pp)
+{
+    const RowGeo& g = h->rgeo;
+    struct Item { int64_t key; int local; float v; };
+    std::vector<Item> items;
+    items.reserve(cells.size());
+    for (auto& e : cells) {
+        const int64_t c = e.first;
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((int64_t)g.nx * g.ny));
+        const int tyi = y / g.ty, zc = z / g.lz;
+        const int64_t b = (int64_t)zc * g.tiles_y + tyi;
+        items.push_back({b * g.lz + (z - zc * g.lz), (y - tyi * g.ty) * g.nx + x, (float)e.second});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b2) { return a.key < b2.key; });
+    const size_t nkeys = (size_t)g.nblocks * g.lz;
+    std::vector<int> off(nkeys + 1, 0);
+    for (auto& it : items) off[it.key + 1]++;
+    for (size_t k = 0; k < nkeys; ++k) off[k + 1] += off[k];
+    std::vector<int2> ent(items.size());
+    std::vector<float> val(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        ent[k] = make_int2(items[k].local, pp);
+        val[k] = items[k].v;
+    }
+    const size_t ms = items.size();
+    if (hipMalloc((void**)&h->rsrc_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->rsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->rsrc_val, std::max<size_t>(ms, 1) * sizeof(float)) != hipSuccess)
+        return LBEM_ENOMEM;
+    hipError_t e = hipMemcpy(h->rsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->rsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->rsrc_val, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->nrsrc = (int64_t)ms;
     return LBEM_OK;
 }
 
@@ -1351,7 +1465,8 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     if (h->zmarch) {
         std::vector<std::pair<int64_t, double>> cv(merged.size());
         for (size_t k = 0; k < merged.size(); ++k) cv[k] = {merged[k].first, src_value[k]};
-        const int rc = build_zmarch_source(h, cv, pp);
+        int rc = build_zmarch_source(h, cv, pp);
+        if (rc == LBEM_OK && h->rowk) rc = build_row_source(h, cv, pp);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
     if (fused_format(h) && h->fuse_ns > 1) {

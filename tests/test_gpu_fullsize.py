@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 def sampled_parity(p, prec, k, samples, tol, streaming="auto"):
     s = lbem.Solver(p.dim, p.shape, prec, w0_vac=p.w0_vac, streaming=streaming)
     s.setup(p)
+    spl = s.steps_per_launch
     s.step(k, p.amp[:k])
     Eg, Bg = s.moments()
     s.close()
@@ -40,6 +41,7 @@ def sampled_parity(p, prec, k, samples, tol, streaming="auto"):
         announce(f"  sample {tuple(int(v) for v in centre)}: max abs diff / window field scale = {err:.2e}")
         worst = max(worst, err)
     assert worst <= tol, worst
+    return spl
 
 
 def test_config2_full_grid_1000_steps_fp32():
@@ -111,3 +113,16 @@ def test_config4_full_512_deviation_storage(prec):
     announce(f"config4 512^3 {prec} full size")
     samples = [(256, 256, 256), (255, 258, 250), (511, 0, 300)]
     sampled_parity(p, prec, k, samples, 1e-3)
+
+
+def test_config4_full_512_fp32_fused_pair():
+    """The FP32 path at 512^3 in the launch configuration bench.py times for
+    it: two fused steps per launch (z-marching frames), streaming stores of
+    the state, row-major tile order (no XCD remap above 4e7 cells), 32-bit
+    local offsets.  16 steps, samples at the dipole, near it, and on the
+    periodic seams of all three axes."""
+    k = 16
+    p = inputs.config4(nsteps=k)
+    announce("config4 512^3 fp32 fused pair, full size")
+    samples = [(256, 256, 256), (250, 261, 253), (511, 0, 300), (0, 511, 0), (3, 255, 511)]
+    assert sampled_parity(p, "f32", k, samples, 1e-5) == 2

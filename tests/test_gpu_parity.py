@@ -181,6 +181,7 @@ def test_streaming_cache_policy_bitwise(shape, mu):
                  ("f32", "aa", {}), ("f32", "pull", {"LBEM_FUSE3": 1}), ("f32", "pull", {"LBEM_FUSE3": 2}),
                  ("f16", "aa", {}), ("f16", "pull", {})]
         cases += [(q, "pull", {"LBEM_DEV3Z": z}) for q in LOWP for z in (0, 1)]
+        cases += [(q, "pull", {"LBEM_DEV3Z": 1, "LBEM_DEV3R": 0}) for q in LOWP]
     else:
         cases = [("f64", "aa", {}), ("f64", "pull", {"LBEM_FUSE": 1}), ("f64", "pull", {"LBEM_FUSE": 2}),
                  ("f32", "aa", {}), ("f32", "pull", {"LBEM_FUSE": 1}), ("f32", "pull", {"LBEM_FUSE": 2}),
@@ -376,8 +377,9 @@ def test_deviation_tile_orders_bitwise(prec):
     p = random_problem(3, (64, 48, 10), seed=95, nsteps=30)
     ref = gpu_run(p, 30, prec, env={"LBEM_STRIP": 0, "LBEM_DEV3Z": 0}).moments()
     for env in ({"LBEM_STRIP": 4, "LBEM_DEV3Z": 0}, {"LBEM_STRIP": 2, "LBEM_XCD": 0, "LBEM_DEV3Z": 0},
-                {"LBEM_VEC": 2, "LBEM_STRIP": 3, "LBEM_DEV3Z": 0}, {"LBEM_DEV3Z": 1},
-                {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 3, "LBEM_DEV3Z_XCD": 0}, {"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": 1}):
+                {"LBEM_VEC": 2, "LBEM_STRIP": 3, "LBEM_DEV3Z": 0}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R": 0},
+                {"LBEM_DEV3Z": 1, "LBEM_DEV3R": 0, "LBEM_DEV3Z_LZ": 3, "LBEM_DEV3Z_XCD": 0},
+                {"LBEM_DEV3Z": 1, "LBEM_DEV3R": 0, "LBEM_DEV3Z_LZ": 1}, {"LBEM_DEV3Z": 1}):
         announce(f"dev tile order {prec} {env}")
         got = gpu_run(p, 30, prec, env=env).moments()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), env
@@ -385,15 +387,42 @@ def test_deviation_tile_orders_bitwise(prec):
 
 @pytest.mark.parametrize("shape,mu", [((19, 13, 11), True), ((70, 5, 9), False), ((130, 9, 3), False)])
 def test_deviation_zmarch_ragged_bitwise(shape, mu):
-    """The z-marching 3D deviation kernel equals the per-cell gather kernel on
-    ragged boxes (tiles wider than the box, chunks longer than nz, mu term)."""
+    """The column-tile z-marching 3D deviation kernel equals the per-cell
+    gather kernel on ragged boxes (tiles wider than the box, chunks longer
+    than nz, mu term)."""
     p = random_problem(3, shape, seed=sum(shape), mu=mu, nsteps=21)
     for prec in LOWP:
         ref = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 0}).moments()
         for lz in (16, 4):
             announce(f"zmarch {shape} mu={mu} {prec} lz={lz}")
-            got = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 1, "LBEM_DEV3Z_LZ": lz}).moments()
+            got = gpu_run(p, 21, prec, env={"LBEM_DEV3Z": 1, "LBEM_DEV3R": 0, "LBEM_DEV3Z_LZ": lz}).moments()
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (prec, lz)
+
+
+@pytest.mark.parametrize("shape,mu", [((64, 40, 20), True), ((100, 9, 7), False), ((600, 3, 5), False),
+                                      ((70, 1, 3), True), ((33, 17, 37), False), ((128, 6, 1), False),
+                                      ((1024, 2, 3), False)])
+def test_deviation_row_kernel_bitwise(shape, mu):
+    """The whole-row z-marching 3D deviation kernel (every stored cell read and
+    decoded once, in-plane populations exchanged through LDS, +-z ones carried
+    in registers along the march) leaves the same state, bit for bit, as the
+    per-cell gather kernel: every 16-bit format, sources spread over many
+    tiles and planes, mu, ragged rows and tiles, one-row and one-plane boxes,
+    rows up to the 1024-cell limit (two rows per tile), chunk lengths and
+    block orders."""
+    p = random_problem(3, shape, seed=sum(shape) + 51, mu=mu, nsteps=23)
+    for prec in LOWP:
+        ref = gpu_run(p, 23, prec, env={"LBEM_DEV3Z": 0})
+        want = ref.get_state()
+        ref.close()
+        for env in ({"LBEM_DEV3Z": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_LZ": 3, "LBEM_DEV3R_XCD": 0},
+                    {"LBEM_DEV3Z": 1, "LBEM_DEV3R_LZ": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_NT": 512},
+                    {"LBEM_DEV3Z": 1, "LBEM_DEV3R_NT": 256, "LBEM_DEV3R_LZ": 2}):
+            announce(f"row kernel {shape} mu={mu} {prec} {env}")
+            s = gpu_run(p, 23, prec, env=dict(env, LBEM_DEV3R=1))
+            got = s.get_state()
+            s.close()
+            assert got.shape == want.shape and np.array_equal(got, want), (prec, env)
 
 
 def test_moments_on_device():

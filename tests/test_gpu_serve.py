@@ -114,3 +114,42 @@ def test_serving_mix_results_equal_solo_runs():
             assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), r.rid
     finally:
         ex.close()
+
+
+def test_batched_members_match_the_oracle():
+    """Members of one batch, advanced together over several ticks with
+    different step counts per tick, against the FP64 oracle at each format's
+    bar: 2D and 3D, FP64 / FP32 (pull and AA) and the FP16 deviation format,
+    on smooth heterogeneous media with a Gaussian pulse (the serving
+    workload's kind of input)."""
+    import torch
+    from gpu_util import oracle_run, rel
+    st = torch.cuda.Stream()
+    batch = serve.Batch(8, 9, st)
+    rng = np.random.default_rng(77)
+    cases = [(2, 96, "f64", "aa"), (2, 128, "f32", "pull"), (2, 80, "f16dev", "pull"),
+             (3, 24, "f32", "aa"), (3, 32, "f16dev", "pull"), (3, 20, "f64", "pull")]
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3}
+    probs, solvers = [], []
+    for dim, n, prec, streaming in cases:
+        shp = (n, n) if dim == 2 else (n, n, n)
+        eps = 1.0 + 3.0 * inputs.smooth_noise(rng, shp, n / 8.0)
+        p = inputs.pulse_problem(dim, n, n / 8.0, rng, eps=eps)
+        s = lbem.Solver(dim, p.shape, prec, streaming=streaming, stream=st)
+        s.setup(p)
+        probs.append(p)
+        solvers.append(s)
+    plan = [[9, 9, 9, 9, 9, 9], [9, 4, 9, 9, 0, 9], [9, 9, 9, 5, 9, 9], [3, 9, 9, 9, 9, 9]]
+    total = np.sum(plan, axis=0)
+    for ns in plan:
+        batch.run(solvers, ns)
+    for k, (dim, n, prec, streaming) in enumerate(cases):
+        Eg, Bg = solvers[k].moments()
+        o = oracle_run(probs[k], int(total[k]))
+        Eo, Bo = o.fields()
+        eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+        announce(f"batched member {dim}d {n} {prec} {streaming} steps={total[k]}: E {eE:.2e} B {eB:.2e}")
+        assert eE <= tol[prec] and eB <= tol[prec], (prec, eE, eB)
+    for s in solvers:
+        s.close()
+    batch.close()
