@@ -293,8 +293,8 @@ const char* lbem_strerror(int code);
  * A batch advances several independent handles together: each step of a tick
  * is one persistent launch per (dim, format) class that strides over all
  * (lattice, tile) work items of the handles in that class.  A tick is
- * steps_per_tick such steps, captured once as a HIP graph per set of classes
- * present and replayed; the per-lattice table it reads is uploaded before each
+ * steps_per_tick such steps; each class's steps are captured once, when the
+ * batch is created, as a HIP graph, and the classes present are replayed; the per-lattice table it reads is uploaded before each
  * tick, so lattices can join and leave between ticks.  Results are bit-for-bit
  * those of lbem_step on each handle alone.
  */
@@ -308,14 +308,26 @@ typedef struct lbem_batch_s* lbem_batch_t;
 int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_batch_t* out);
 
 /* Enqueue one tick on the batch stream: handle k advances by nsteps[k] steps
- * (0 <= nsteps[k] <= steps_per_tick; 0 leaves it untouched).  Members must be
- * distinct, initialised (ESTATE otherwise), created with pull streaming (or AA
- * for the plain formats) in a format up to LBEM_BF16DEV, periodic, without a
- * current source, mu == 1, and none of the cell extras (EINVAL otherwise).  Returns once enqueued; lbem_moments on a member
- * synchronises.
- * The host-side table is double-buffered: a call waits only for the upload of
- * the tick before the previous one. */
+ * (0 <= nsteps[k] <= steps_per_tick; 0 leaves it untouched), each step the
+ * lattice-BGK update of lbem_step (eqs. LBE, COLLI, STREAM), current source
+ * and non-uniform mu term included.  Members must be distinct, initialised
+ * (ESTATE otherwise), periodic with none of the cell extras (walls, absorber,
+ * dispersion, anisotropy), created with pull streaming (or AA for the plain
+ * formats LBEM_F64, LBEM_F32, LBEM_F16), any format (EINVAL otherwise).  A
+ * member's current source runs at amplitude 0 here (as lbem_step with
+ * amp == NULL); lbem_batch_run_amp gives the amplitudes.  Returns once
+ * enqueued; lbem_moments on a member synchronises.  The host-side table is
+ * double-buffered: a call waits only for the upload of the tick before the
+ * previous one. */
 int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count);
+
+/* lbem_batch_run with source amplitudes: amp (host, count * steps_per_tick
+ * doubles, row k for handle k) gives amp[k*steps_per_tick + j] to the j-th
+ * step of handle k in this tick, as lbem_step's amp does for a solo call (the
+ * current density of the forcing of Subsection "Homogeneous media").  Rows of
+ * handles without a source are ignored; amp == NULL is lbem_batch_run. */
+int lbem_batch_run_amp(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, const double* amp,
+                       int count);
 
 /* Destroy a batch (NULL accepted); synchronises its stream. */
 int lbem_batch_destroy(lbem_batch_t b);

@@ -498,6 +498,167 @@ __global__ __launch_bounds__(NT) void k_step_plain(const S* src, S* dst, const T
 }
 
 // ---------------------------------------------------------------------------
+// 3D plain formats, single step on whole-row blocks
+// ---------------------------------------------------------------------------
+// A block of NT threads owns `rows` whole x-rows of one plane; a thread owns
+// CX cells of one row (x = q + k*tpr).  The populations that move along y or
+// z are read from (and, pushed, written to) the neighbouring rows directly:
+// those rows are aligned to the same x, so every access is a whole, aligned
+// row segment.  The ones that move along x go through LDS: a thread loads
+// (and stores) the slot at its own cell and the row shifts by one in LDS, so
+// no load or store straddles cache lines.  With the in-place AA pattern each
+// stored location is still read and written by one thread only.  The
+// arithmetic is k_step_plain's, so the two agree bit for bit.
+struct XRowGeo {
+    int nx, ny, nz;
+    int tpr, rows;       // threads per row (multiple of 64, CX*tpr >= nx), rows per block (NT / tpr)
+    int tiles_y, nblocks;
+    int64_t n;
+};
+
+template <typename T, int RM, int WM, bool MU, typename S, bool NTS, int CX>
+__global__ __launch_bounds__(NT) void k_step_xrow(const S* src, S* dst, const T* __restrict__ cl2a,
+                                                 const T* __restrict__ dlnmu, const XRowGeo g,
+                                                 const int* __restrict__ soff, const int2* __restrict__ sent,
+                                                 const T* __restrict__ sval, const T amp, const T omega,
+                                                 const int tau_half)
+{
+    constexpr int D = 3, Q = 7, P = 3;
+    constexpr int RC = CX * NT;               // cells of the block
+    __shared__ T lx[2 * P * RC];              // [side*P + p][row*nx + x]
+    const int b = blockIdx.x;
+    const int yt = b % g.tiles_y, z = b / g.tiles_y;
+    const int y0 = yt * g.rows;
+    const int nx = g.nx;
+    const int r = threadIdx.x / g.tpr, q = threadIdx.x % g.tpr;
+    const int y = y0 + r;
+    const bool row_ok = r < g.rows && y < g.ny;
+    const int64_t n = g.n;
+    int xs[CX];
+    bool ok[CX];
+#pragma unroll
+    for (int k = 0; k < CX; ++k) {
+        xs[k] = q + k * g.tpr;
+        ok[k] = row_ok && xs[k] < nx;
+    }
+    // the slot that arrives along +x (side 0) and -x (side 1), read at the own cell
+    constexpr int in_p = RM == R_PULL_SWAP ? 4 : 1;   // arrives along +x: slot 1 (pull) / 4 (AA odd)
+    constexpr int in_m = RM == R_PULL_SWAP ? 1 : 4;
+    constexpr bool XIN = RM != R_LOCAL;
+    constexpr bool XOUT = WM == W_PUSH;
+
+    T f[CX][Q][P];
+#pragma unroll
+    for (int k = 0; k < CX; ++k) {
+        if (!ok[k]) continue;
+        Cell C = make_cell(Geo{nx, g.ny, g.nz, 0, 0, 0, 0, 0, 0, n}, xs[k], y, z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const bool along_x = i == 1 || i == 4;
+            if (XIN && along_x) continue;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                f[k][i][p] = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(read_slot<D, RM>(i) * P + p) * n + read_cell<D, RM>(C, i)]));
+        }
+        if constexpr (XIN) {
+            const int loc = r * nx + xs[k];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                lx[(0 * P + p) * RC + loc] = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(in_p * P + p) * n + C.c]));
+                lx[(1 * P + p) * RC + loc] = ld_pop<T>(ld_stream<NTS>(&src[(int64_t)(in_m * P + p) * n + C.c]));
+            }
+        }
+    }
+    if constexpr (XIN) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            const int x = xs[k];
+            const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                f[k][1][p] = lx[(0 * P + p) * RC + r * nx + xm];    // from x-1
+                f[k][4][p] = lx[(1 * P + p) * RC + r * nx + xp];    // from x+1
+            }
+        }
+        __syncthreads();
+    }
+    // source entries of this block: (row*nx + x, pair)
+    int s0 = 0, s1 = 0;
+    if (soff) {
+        s0 = soff[b];
+        s1 = soff[b + 1];
+    }
+    const bool has_src = s1 > s0;
+    T out[CX][Q][P];
+#pragma unroll
+    for (int k = 0; k < CX; ++k) {
+        if (!ok[k]) continue;
+        const int64_t c = (int64_t)z * ((int64_t)nx * g.ny) + (int64_t)y * nx + xs[k];
+        const T cl2 = cl2a[c];
+        T rho[P], K[D], Sp[P];
+        moments<D, T>(f[k], rho, K);
+#pragma unroll
+        for (int p = 0; p < P; ++p) Sp[p] = T(0);
+        const int loc = r * nx + xs[k];
+        for (int e = s0; e < s1; ++e) {
+            const int2 en = sent[e];
+            if (en.x == loc) {
+                const T v = sval[e] * amp;
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    if (en.y == p) Sp[p] = v;
+            }
+        }
+        if (MU) {
+            T dl[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * n + c];
+            add_mu_source<D, T>(K, cl2, dl, Sp);
+        }
+        collide<D, T>(f[k], cl2, Sp, has_src || MU, omega, tau_half != 0, rho, K, out[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < CX; ++k) {
+        if (!ok[k]) continue;
+        Cell C = make_cell(Geo{nx, g.ny, g.nz, 0, 0, 0, 0, 0, 0, n}, xs[k], y, z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const bool along_x = i == 1 || i == 4;
+            if (XOUT && along_x) continue;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                st_stream<NTS>(&dst[(int64_t)(write_slot<D, WM>(i) * P + p) * n + write_cell<D, WM>(C, i)],
+                               st_pop<S>(out[k][i][p]));
+        }
+        if constexpr (XOUT) {
+            const int x = xs[k];
+            const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                lx[(0 * P + p) * RC + r * nx + xp] = out[k][1][p];   // pushed to x+1
+                lx[(1 * P + p) * RC + r * nx + xm] = out[k][4][p];   // pushed to x-1
+            }
+        }
+    }
+    if constexpr (XOUT) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CX; ++k) {
+            if (!ok[k]) continue;
+            const int64_t c = (int64_t)z * ((int64_t)nx * g.ny) + (int64_t)y * nx + xs[k];
+            const int loc = r * nx + xs[k];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                st_stream<NTS>(&dst[(int64_t)(1 * P + p) * n + c], st_pop<S>(lx[(0 * P + p) * RC + loc]));
+                st_stream<NTS>(&dst[(int64_t)(4 * P + p) * n + c], st_pop<S>(lx[(1 * P + p) * RC + loc]));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 2D temporal blocking: NS time steps per launch (plain formats, pull)
 // ---------------------------------------------------------------------------
 // A block owns an output tile of TXF x TY cells.  All work happens in one LDS
@@ -1919,7 +2080,12 @@ struct BatchGrid {
     void* buf[2];        // plain: population copies; dev: moment arrays
     void* dev[2];        // dev: deviation arrays (unused for plain)
     const void* cl2;
-    Geo geo;             // VEC = 1 tiling, no XCD remap, no strip order
+    const void* dlnmu;   // grad ln mu [D][n] (medium precision) when mu varies, else nullptr
+    const int* src_off;  // the member's sparse current source, per tile of its own tiling, or nullptr
+    const int2* src_ent;
+    const void* src_val;
+    const void* amp;     // [nsteps] source amplitudes of this tick (arithmetic type), or nullptr (zero)
+    Geo geo;             // the member's own tiling (VEC = 1); tile ids match its source table
     double omega;
     int tau_half;
     int cur0;            // copy holding the state when the tick starts
@@ -1946,8 +2112,22 @@ __device__ __forceinline__ int batch_find(const BatchGrid* __restrict__ tab, int
     return lo;
 }
 
-template <int D, typename T, int RM, int WM>
-__device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, int k)
+// Source of one tile of a member (the staging of the single-step kernels):
+// every thread of the block takes part, before any of them leaves the tile.
+template <int P, typename T>
+__device__ __forceinline__ bool batch_source(const BatchGrid& G, int tile, int k, T* lds)
+{
+    SrcArgs<T> s;
+    s.off = G.src_off;
+    s.ent = G.src_ent;
+    s.val = (const T*)G.src_val;
+    s.amp = G.amp ? ((const T*)G.amp)[k] : T(0);
+    return stage_source<P, 1, T>(s, tile, lds);
+}
+
+// S: storage type of the populations (T itself, or FP16 under FP32 arithmetic)
+template <int D, typename T, int RM, int WM, typename S>
+__device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, int k, T* lds)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     const Geo& g = G.geo;
@@ -1956,33 +2136,41 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
     const int bx = 1 << g.bx_shift;
     const int x = tx * bx + (threadIdx.x & (bx - 1));
     const int y = ty * (NT >> g.bx_shift) + (threadIdx.x >> g.bx_shift);
+    const bool has_src = batch_source<P, T>(G, tile, k, lds);
+    const bool mu = G.dlnmu != nullptr;
     if (x >= g.nx || y >= g.ny) return;
     const int s = G.aa ? 0 : (G.cur0 + k) & 1;
-    const T* src = (const T*)G.buf[s];
-    T* dst = (T*)G.buf[G.aa ? 0 : s ^ 1];     // AA: in place, each location read and written by one thread
+    const S* src = (const S*)G.buf[s];
+    S* dst = (S*)G.buf[G.aa ? 0 : s ^ 1];     // AA: in place, each location read and written by one thread
     const Cell C = make_cell(g, x, y, z);
     T f[Q][P];
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            f[i][p] = src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)];
+            f[i][p] = ld_pop<T>(src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]);
     const T cl2 = ((const T*)G.cl2)[C.c];
     T rho[P], K[D], Sp[P];
     moments<D, T>(f, rho, K);
 #pragma unroll
-    for (int p = 0; p < P; ++p) Sp[p] = T(0);
+    for (int p = 0; p < P; ++p) Sp[p] = has_src ? lds[p * NT + threadIdx.x] : T(0);
+    if (mu) {
+        T dl[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dl[a] = ((const T*)G.dlnmu)[(int64_t)a * g.n + C.c];
+        add_mu_source<D, T>(K, cl2, dl, Sp);
+    }
     T out[Q][P];
-    collide<D, T>(f, cl2, Sp, false, (T)G.omega, G.tau_half != 0, rho, K, out);
+    collide<D, T>(f, cl2, Sp, has_src || mu, (T)G.omega, G.tau_half != 0, rho, K, out);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = out[i][p];
+            dst[(int64_t)(write_slot<D, WM>(i) * P + p) * g.n + write_cell<D, WM>(C, i)] = st_pop<S>(out[i][p]);
 }
 
-template <int D, typename H, int RM>
-__device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int k)
+template <int D, typename H, bool GH, int RM>
+__device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int k, float* lds)
 {
     constexpr int Q = Lat<D>::Q, P = Lat<D>::P;
     const Geo& g = G.geo;
@@ -1991,6 +2179,8 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
     const int bx = 1 << g.bx_shift;
     const int x = tx * bx + (threadIdx.x & (bx - 1));
     const int y = ty * (NT >> g.bx_shift) + (threadIdx.x >> g.bx_shift);
+    const bool has_src = batch_source<P, float>(G, tile, k, lds);
+    const bool mu = G.dlnmu != nullptr;
     if (x >= g.nx || y >= g.ny) return;
     const int s = (G.cur0 + k) & 1;
     const float* Min = (const float*)G.buf[s];
@@ -2005,20 +2195,27 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
     for (int i = 0; i < Q; ++i)
 #pragma unroll
         for (int p = 0; p < P; ++p)
-            f[i][p] = dev_load<D, H, false>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
+            f[i][p] = dev_load<D, H, GH>(Min, Din, g.n, i, p, read_cell<D, RM>(C, i), wc0);
     float rho[P], K[D], Sp[P];
     moments<D, float>(f, rho, K);
 #pragma unroll
-    for (int p = 0; p < P; ++p) Sp[p] = 0.f;
-    dev_collide_store<D, H, false>(f, cl2, wc0, Sp, false, (float)G.omega, G.tau_half != 0, rho, K, g.n, C.c,
-                                   Mout, Dout);
+    for (int p = 0; p < P; ++p) Sp[p] = has_src ? lds[p * NT + threadIdx.x] : 0.f;
+    if (mu) {
+        float dl[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) dl[a] = ((const float*)G.dlnmu)[(int64_t)a * g.n + C.c];
+        add_mu_source<D, float>(K, cl2, dl, Sp);
+    }
+    dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, has_src || mu, (float)G.omega, G.tau_half != 0, rho, K, g.n,
+                                C.c, Mout, Dout);
 }
 
 // Launch k of a tick: every lattice with k < nsteps advances one step.
-template <int D, typename T>
+template <int D, typename T, typename S = T>
 __global__ __launch_bounds__(NT) void k_step_batch_plain(const BatchHdr* __restrict__ hdr,
                                                         const BatchGrid* __restrict__ tab, int k)
 {
+    __shared__ T lds[Lat<D>::P * NT];
     const int count = hdr->count, total = hdr->total_tiles;
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
         const int gi = batch_find(tab, count, w);
@@ -2026,27 +2223,30 @@ __global__ __launch_bounds__(NT) void k_step_batch_plain(const BatchHdr* __restr
         if (k >= G.nsteps) continue;
         if (G.aa) {
             // even steps from the natural layout, odd ones from the swapped one
-            if ((G.fresh != 0) == ((k & 1) == 0)) batch_tile_plain<D, T, R_LOCAL, W_SWAP>(G, w - G.tile_base, k);
-            else batch_tile_plain<D, T, R_PULL_SWAP, W_PUSH>(G, w - G.tile_base, k);
+            if ((G.fresh != 0) == ((k & 1) == 0)) batch_tile_plain<D, T, R_LOCAL, W_SWAP, S>(G, w - G.tile_base, k, lds);
+            else batch_tile_plain<D, T, R_PULL_SWAP, W_PUSH, S>(G, w - G.tile_base, k, lds);
         } else if (G.fresh && k == 0) {
-            batch_tile_plain<D, T, R_LOCAL, W_LOCAL>(G, w - G.tile_base, k);
+            batch_tile_plain<D, T, R_LOCAL, W_LOCAL, S>(G, w - G.tile_base, k, lds);
         } else {
-            batch_tile_plain<D, T, R_PULL, W_LOCAL>(G, w - G.tile_base, k);
+            batch_tile_plain<D, T, R_PULL, W_LOCAL, S>(G, w - G.tile_base, k, lds);
         }
+        __syncthreads();   // the next work item may stage its source into lds
     }
 }
 
-template <int D, typename H>
+template <int D, typename H, bool GH>
 __global__ __launch_bounds__(NT) void k_step_batch_dev(const BatchHdr* __restrict__ hdr,
                                                       const BatchGrid* __restrict__ tab, int k)
 {
+    __shared__ float lds[Lat<D>::P * NT];
     const int count = hdr->count, total = hdr->total_tiles;
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
         const int gi = batch_find(tab, count, w);
         const BatchGrid& G = tab[gi];
         if (k >= G.nsteps) continue;
-        if (G.fresh && k == 0) batch_tile_dev<D, H, R_LOCAL>(G, w - G.tile_base, k);
-        else batch_tile_dev<D, H, R_PULL>(G, w - G.tile_base, k);
+        if (G.fresh && k == 0) batch_tile_dev<D, H, GH, R_LOCAL>(G, w - G.tile_base, k, lds);
+        else batch_tile_dev<D, H, GH, R_PULL>(G, w - G.tile_base, k, lds);
+        __syncthreads();   // the next work item may stage its source into lds
     }
 }
 

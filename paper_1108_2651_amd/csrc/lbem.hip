@@ -152,6 +152,13 @@ struct lbem_s {
     int2* zsrc_ent;
     void* zsrc_val;
     int64_t nzsrc;
+    // 3D plain single steps on whole-row blocks (k_step_xrow)
+    int xrow;
+    XRowGeo xgeo;
+    int* xsrc_off;
+    int2* xsrc_ent;
+    void* xsrc_val;
+    int64_t nxsrc;
     // 3D deviation kernel on whole-row tiles (k_step_dev3r), marching along z
     int rowk;
     RowGeo rgeo;
@@ -372,9 +379,22 @@ static bool fused_ok(const lbem_s* h)
 // plain formats: populations stored as S, arithmetic in T
 template <int D, typename T, typename S = T>
 struct PlainImpl : Impl {
+    template <int RM, int WM, bool MU, bool NTS>
+    static hipError_t go_xrow(lbem_s* h, const S* src, S* dst, T amp)
+    {
+        hipLaunchKernelGGL((k_step_xrow<T, RM, WM, MU, S, NTS, 2>), dim3(h->xgeo.nblocks), dim3(NT), 0, h->stream,
+                           src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->xgeo,
+                           h->nxsrc ? h->xsrc_off : nullptr, h->xsrc_ent, (const T*)h->xsrc_val, amp,
+                           (T)(1.0 / h->cfg.tau), (int)(h->cfg.tau == 0.5));
+        return hipGetLastError();
+    }
     template <int RM, int WM, int V, bool MU, bool BX = false>
     static hipError_t go(lbem_s* h, const S* src, S* dst, T amp)
     {
+        if constexpr (D == 3 && !BX && V == 1) {
+            if (h->xrow) return h->nts ? go_xrow<RM, WM, MU, true>(h, src, dst, amp)
+                                       : go_xrow<RM, WM, MU, false>(h, src, dst, amp);
+        }
         SrcArgs<T> s;
         s.off = h->nsrc ? h->src_off : nullptr;
         s.ent = h->src_ent;
@@ -742,6 +762,30 @@ static void make_zmarch_geo(lbem_s* h)
     g.xcd = env_int("LBEM_DEV3Z_XCD", 0);
 }
 
+// Whole-row blocks of k_step_xrow (3D plain formats, single steps without
+// cell extras): CX = 2 cells per thread, tpr threads per row, NT/tpr rows per
+// block, one plane.  Measured (same box, per step): plain FP16 AA 2.33 -> 2.15
+// ms at 512^3 and 0.261 -> 0.244 ms at 256^3, where a 64-wide row of 16-bit
+// values is one cache line and a shifted one touches two; FP32 AA and pull
+// within +-3 % at 256^3 and 512^3; every format slower while the state is
+// Infinity-Cache resident (128^3).  So the default takes it for FP16 storage
+// beyond 6e6 cells; LBEM_XROW=1 selects it for the others.
+static void make_xrow_geo(lbem_s* h)
+{
+    const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
+    const bool plain = h->prec <= LBEM_F32 || h->prec == LBEM_F16;
+    const int dflt = h->prec == LBEM_F16 && (double)h->n >= SMALL3D;
+    h->xrow = (h->D == 3 && plain && nx <= 2 * NT && h->vec == 1) ? env_int("LBEM_XROW", dflt) : 0;
+    XRowGeo& g = h->xgeo;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
+    int tpr = 64;
+    while (2 * tpr < nx) tpr <<= 1;
+    g.tpr = tpr;
+    g.rows = NT / tpr;
+    g.tiles_y = (ny + g.rows - 1) / g.rows;
+    g.nblocks = g.tiles_y * nz;
+}
+
 // Whole-row tiles of k_step_dev3r: CX = 2 cells per thread, tpr threads per
 // row (a power of two from 64 up to the block size), ty = block/tpr rows per
 // tile; z chunks as long as still give >= 1024 blocks.  Rows longer than
@@ -914,6 +958,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     make_fused_geo(h);
     make_zmarch_geo(h);
     make_row_geo(h);
+    make_xrow_geo(h);
     // Measured: streaming loads/stores slow a launch whose state fits the
     // 256 MB Infinity Cache (by up to 1.8x) and speed it up beyond that: in 3D
     // from about 1.5 times the cache on (2-10 %; at 344 MB still 9 % slower),
@@ -954,6 +999,11 @@ static void free_source(lbem_s* h)
     if (h->zsrc_off) (void)hipFree(h->zsrc_off);
     if (h->zsrc_ent) (void)hipFree(h->zsrc_ent);
     if (h->zsrc_val) (void)hipFree(h->zsrc_val);
+    if (h->xsrc_off) (void)hipFree(h->xsrc_off);
+    if (h->xsrc_ent) (void)hipFree(h->xsrc_ent);
+    if (h->xsrc_val) (void)hipFree(h->xsrc_val);
+    h->xsrc_off = nullptr; h->xsrc_ent = nullptr; h->xsrc_val = nullptr;
+    h->nxsrc = 0;
     if (h->rsrc_off) (void)hipFree(h->rsrc_off);
     if (h->rsrc_ent) (void)hipFree(h->rsrc_ent);
     if (h->rsrc_val) (void)hipFree(h->rsrc_val);
@@ -1097,6 +1147,49 @@ static int build_row_source(lbem_s* h, const std::vector<std::pair<int64_t, doub
     if (e == hipSuccess && ms) e = hipMemcpy(h->rsrc_val, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return LBEM_EDEVICE;
     h->nrsrc = (int64_t)ms;
+    return LBEM_OK;
+}
+
+// Source entries of the whole-row plain tiling: per block (tiles_y * z + row
+// tile) the cells (row * nx + x) that carry a current, with S per unit amplitude.
+static int build_xrow_source(lbem_s* h, const std::vector<std::pair<int64_t, double>>& cells, int pp)
+{
+    const XRowGeo& g = h->xgeo;
+    struct Item { int b; int local; double v; };
+    std::vector<Item> items;
+    items.reserve(cells.size());
+    for (auto& e : cells) {
+        const int64_t c = e.first;
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((int64_t)g.nx * g.ny));
+        const int yt = y / g.rows;
+        items.push_back({z * g.tiles_y + yt, (y - yt * g.rows) * g.nx + x, e.second});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b2) { return a.b < b2.b; });
+    std::vector<int> off((size_t)g.nblocks + 1, 0);
+    for (auto& it : items) off[it.b + 1]++;
+    for (int b = 0; b < g.nblocks; ++b) off[b + 1] += off[b];
+    std::vector<int2> ent(items.size());
+    for (size_t k = 0; k < items.size(); ++k) ent[k] = make_int2(items[k].local, pp);
+    const size_t ms = items.size(), tv = h->prec == LBEM_F64 ? 8 : 4;
+    if (hipMalloc((void**)&h->xsrc_off, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->xsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->xsrc_val, std::max<size_t>(ms, 1) * tv) != hipSuccess)
+        return LBEM_ENOMEM;
+    hipError_t e = hipMemcpy(h->xsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(h->xsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) {
+        if (tv == 8) {
+            std::vector<double> v(ms);
+            for (size_t k = 0; k < ms; ++k) v[k] = items[k].v;
+            e = hipMemcpy(h->xsrc_val, v.data(), ms * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> v(ms);
+            for (size_t k = 0; k < ms; ++k) v[k] = (float)items[k].v;
+            e = hipMemcpy(h->xsrc_val, v.data(), ms * 4, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) return LBEM_EDEVICE;
+    h->nxsrc = (int64_t)ms;
     return LBEM_OK;
 }
 
@@ -1469,6 +1562,12 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
         if (rc == LBEM_OK && h->rowk) rc = build_row_source(h, cv, pp);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
+    if (h->xrow) {
+        std::vector<std::pair<int64_t, double>> cv(merged.size());
+        for (size_t k = 0; k < merged.size(); ++k) cv[k] = {merged[k].first, src_value[k]};
+        const int rc = build_xrow_source(h, cv, pp);
+        if (rc != LBEM_OK) { free_source(h); return rc; }
+    }
     if (fused_format(h) && h->fuse_ns > 1) {
         std::vector<double> dense((size_t)n, 0.0);
         for (size_t k = 0; k < merged.size(); ++k) dense[(size_t)merged[k].first] = src_value[k];
@@ -1673,10 +1772,11 @@ int lbem_set_state(lbem_t h, const void* buf, size_t bytes, int on_device)
 // batched stepping of many resident lattices (serving)
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int NCLASS = 8;  // (dim - 2) * 4 + prec
+constexpr int NPREC = 7;   // LBEM_F64 .. LBEM_F16
+constexpr int NCLASS = 2 * NPREC;  // (dim - 2) * NPREC + prec
 constexpr int BATCH_BLOCKS = 8192;  // persistent grid (more blocks than fit: the rest start as others finish)
 
-int class_of(const lbem_s* h) { return (h->D - 2) * 4 + h->prec; }
+int class_of(const lbem_s* h) { return (h->D - 2) * NPREC + h->prec; }
 
 size_t class_bytes(int max_grids) { return align256(sizeof(BatchHdr)) + align256(sizeof(BatchGrid) * (size_t)max_grids); }
 }  // namespace
@@ -1684,7 +1784,8 @@ size_t class_bytes(int max_grids) { return align256(sizeof(BatchHdr)) + align256
 struct lbem_batch_s {
     hipStream_t stream;
     int max_grids, ksteps;
-    char* dev;                 // NCLASS x (header, table)
+    char* dev;                 // NCLASS x (header, table), then the amplitudes [max_grids][ksteps] (8 B each)
+    size_t amp_off;            // offset of the amplitudes
     char* pinned[2];
     hipEvent_t ev[2];
     int ring;
@@ -1696,22 +1797,34 @@ struct lbem_batch_s {
     int blocks;                // persistent grid of each class launch
 };
 
+template <int D>
+static void launch_class_d(lbem_batch_s* b, int prec, const BatchHdr* hdr, const BatchGrid* tab, int k)
+{
+    dim3 g(b->blocks), t(NT);
+    switch (prec) {
+        case LBEM_F64: hipLaunchKernelGGL((k_step_batch_plain<D, double>), g, t, 0, b->stream, hdr, tab, k); break;
+        case LBEM_F32: hipLaunchKernelGGL((k_step_batch_plain<D, float>), g, t, 0, b->stream, hdr, tab, k); break;
+        case LBEM_F16DEV: hipLaunchKernelGGL((k_step_batch_dev<D, __half, false>), g, t, 0, b->stream, hdr, tab, k); break;
+        case LBEM_BF16DEV:
+            hipLaunchKernelGGL((k_step_batch_dev<D, __hip_bfloat16, false>), g, t, 0, b->stream, hdr, tab, k);
+            break;
+        case LBEM_F16GHOST: hipLaunchKernelGGL((k_step_batch_dev<D, __half, true>), g, t, 0, b->stream, hdr, tab, k); break;
+        case LBEM_BF16GHOST:
+            hipLaunchKernelGGL((k_step_batch_dev<D, __hip_bfloat16, true>), g, t, 0, b->stream, hdr, tab, k);
+            break;
+        default:
+            hipLaunchKernelGGL((k_step_batch_plain<D, float, __half>), g, t, 0, b->stream, hdr, tab, k);
+            break;
+    }
+}
+
 static void launch_class(lbem_batch_s* b, int c, int k)
 {
     const size_t cb = class_bytes(b->max_grids);
     const BatchHdr* hdr = (const BatchHdr*)(b->dev + c * cb);
     const BatchGrid* tab = (const BatchGrid*)(b->dev + c * cb + align256(sizeof(BatchHdr)));
-    dim3 g(b->blocks), t(NT);
-    switch (c) {
-        case 0: hipLaunchKernelGGL((k_step_batch_plain<2, double>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 1: hipLaunchKernelGGL((k_step_batch_plain<2, float>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 2: hipLaunchKernelGGL((k_step_batch_dev<2, __half>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 3: hipLaunchKernelGGL((k_step_batch_dev<2, __hip_bfloat16>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 4: hipLaunchKernelGGL((k_step_batch_plain<3, double>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 5: hipLaunchKernelGGL((k_step_batch_plain<3, float>), g, t, 0, b->stream, hdr, tab, k); break;
-        case 6: hipLaunchKernelGGL((k_step_batch_dev<3, __half>), g, t, 0, b->stream, hdr, tab, k); break;
-        default: hipLaunchKernelGGL((k_step_batch_dev<3, __hip_bfloat16>), g, t, 0, b->stream, hdr, tab, k); break;
-    }
+    if (c < NPREC) launch_class_d<2>(b, c, hdr, tab, k);
+    else launch_class_d<3>(b, c - NPREC, hdr, tab, k);
 }
 
 // Capture the per-class graphs.  Done once, at creation, with the library
@@ -1782,7 +1895,8 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     b->ring = 0;
     b->use_graph = env_int("LBEM_BATCH_GRAPH", 1);
     b->blocks = std::max(1, env_int("LBEM_BATCH_BLOCKS", BATCH_BLOCKS));
-    const size_t bytes = class_bytes(max_lattices) * NCLASS;
+    b->amp_off = class_bytes(max_lattices) * NCLASS;
+    const size_t bytes = b->amp_off + align256((size_t)max_lattices * steps_per_tick * 8);
     b->dev = nullptr;
     b->pinned[0] = b->pinned[1] = nullptr;
     b->ev[0] = b->ev[1] = nullptr;
@@ -1834,15 +1948,19 @@ int lbem_batch_destroy(lbem_batch_t b)
 
 int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count)
 {
+    return lbem_batch_run_amp(b, handles, nsteps, nullptr, count);
+}
+
+int lbem_batch_run_amp(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, const double* amp, int count)
+{
     if (!b || count < 0 || count > b->max_grids || (count > 0 && (!handles || !nsteps))) return LBEM_EINVAL;
     for (int i = 0; i < count; ++i) {
         const lbem_s* h = handles[i];
         if (!h || nsteps[i] < 0 || nsteps[i] > b->ksteps) return LBEM_EINVAL;
-        if (h->nsrc != 0 || h->mu_set) return LBEM_EINVAL;
-        if (h->streaming != LBEM_STREAM_PULL && !(h->streaming == LBEM_STREAM_AA && h->prec <= LBEM_F32))
-            return LBEM_EINVAL;
-        if (h->prec > LBEM_BF16DEV) return LBEM_EINVAL;  // no batched ghost-coordinate or plain FP16 kernels
-        if (has_bx(h)) return LBEM_EINVAL;                // periodic boxes only
+        const bool plain = h->prec <= LBEM_F32 || h->prec == LBEM_F16;
+        if (h->streaming != LBEM_STREAM_PULL && !(h->streaming == LBEM_STREAM_AA && plain)) return LBEM_EINVAL;
+        if (has_bx(h)) return LBEM_EINVAL;                // periodic, no cell extras
+        if (h->vec != 1) return LBEM_EINVAL;              // the batch tiles one row of cells per thread
         if (!h->have_fields) return LBEM_ESTATE;
         for (int j = 0; j < i; ++j)
             if (handles[j] == h) return LBEM_EINVAL;
@@ -1853,6 +1971,7 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
     const size_t cb = class_bytes(b->max_grids);
     int cnt[NCLASS] = {0}, tiles[NCLASS] = {0};
     unsigned mask = 0;
+    size_t amp_used = 0;      // end of the amplitudes written for this tick
     for (int i = 0; i < count; ++i) {
         lbem_s* h = handles[i];
         if (nsteps[i] == 0) continue;
@@ -1860,7 +1979,7 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
         BatchGrid* tab = (BatchGrid*)(host + c * cb + align256(sizeof(BatchHdr)));
         BatchGrid& G = tab[cnt[c]++];
         std::memset(&G, 0, sizeof(G));
-        if (h->prec <= LBEM_F32) {
+        if (h->prec <= LBEM_F32 || h->prec == LBEM_F16) {     // plain populations (FP16 storage included)
             const bool aa = h->streaming == LBEM_STREAM_AA;
             G.buf[0] = h->pop[0];
             G.buf[1] = aa ? h->pop[0] : h->pop[1];
@@ -1873,13 +1992,28 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
             G.dev[1] = h->pop[1] + moff;
         }
         G.cl2 = h->cl2;
+        G.dlnmu = h->mu_set ? h->dlnmu : nullptr;
+        // the member's own tiling, so that its per-tile source table applies
         Geo& g = G.geo;
         g = h->geo;
-        const int bx = 1 << g.bx_shift, rb = NT / bx;
-        g.tiles_y = (g.ny + rb - 1) / rb;
-        g.nblocks = g.tiles_x * g.tiles_y * g.nz;
         g.xcd = 0;
-        g.strip = 0;
+        if (h->nsrc) {
+            G.src_off = h->src_off;
+            G.src_ent = h->src_ent;
+            G.src_val = h->src_val;
+            if (amp) {
+                // this member's amplitudes, in the class's arithmetic type
+                char* slot = host + b->amp_off + (size_t)i * b->ksteps * 8;
+                const size_t dslot = b->amp_off + (size_t)i * b->ksteps * 8;
+                for (int64_t j = 0; j < nsteps[i]; ++j) {
+                    const double a = amp[(size_t)i * b->ksteps + j];
+                    if (h->prec == LBEM_F64) ((double*)slot)[j] = a;
+                    else ((float*)slot)[j] = (float)a;
+                }
+                G.amp = b->dev + dslot;
+                amp_used = std::max(amp_used, dslot + (size_t)b->ksteps * 8);
+            }
+        }
         G.omega = 1.0 / h->cfg.tau;
         G.tau_half = h->cfg.tau == 0.5;
         G.cur0 = h->cur;
@@ -1902,7 +2036,8 @@ int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps,
             hipStreamWaitEvent(b->stream, h->sync_ev, 0) != hipSuccess)
             return LBEM_EDEVICE;
     }
-    if (hipMemcpyAsync(b->dev, host, cb * NCLASS, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    if (hipMemcpyAsync(b->dev, host, amp_used ? amp_used : cb * NCLASS, hipMemcpyHostToDevice, b->stream) !=
+        hipSuccess)
         return LBEM_EDEVICE;
     if (hipEventRecord(b->ev[b->ring], b->stream) != hipSuccess) return LBEM_EDEVICE;
     b->ring ^= 1;

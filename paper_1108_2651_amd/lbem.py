@@ -28,7 +28,7 @@ SYMBOLS = ("lbem_required_bytes", "lbem_create", "lbem_destroy", "lbem_set_mediu
            "lbem_time", "lbem_strerror", "lbem_batch_create", "lbem_batch_run", "lbem_batch_destroy",
            "lbem_steps_per_launch", "lbem_state_bytes", "lbem_get_state", "lbem_set_state",
            "lbem_set_boundary", "lbem_set_absorber", "lbem_set_dispersion", "lbem_set_anisotropy",
-           "lbem_energy_noalloc")
+           "lbem_energy_noalloc", "lbem_batch_run_amp")
 BOUNDARY = {"periodic": 0, "pec": 1, "pmc": 2}
 
 

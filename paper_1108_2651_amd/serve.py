@@ -35,6 +35,8 @@ def _batch_lib():
     if not getattr(L, "_batch_typed", False):
         L.lbem_batch_create.argtypes = [C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
         L.lbem_batch_run.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int]
+        L.lbem_batch_run_amp.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_double), C.c_int]
         L.lbem_batch_destroy.argtypes = [C.c_void_p]
         L._batch_typed = True
     return L
@@ -54,11 +56,23 @@ class Batch:
             raise lbem.LbemError(rc, "lbem_batch_create")
         self._h = h
 
-    def run(self, solvers, nsteps):
+    def run(self, solvers, nsteps, amps=None):
+        """One tick: solver k advances nsteps[k] steps.  amps: per solver None
+        or the source amplitudes of its steps in this tick (lbem_batch_run_amp)."""
         n = len(solvers)
         hs = (C.c_void_p * max(n, 1))(*[s._h for s in solvers])
         ns = (C.c_int64 * max(n, 1))(*[int(k) for k in nsteps])
-        rc = _batch_lib().lbem_batch_run(self._h, hs, ns, n)
+        if amps is None or all(a is None for a in amps):
+            rc = _batch_lib().lbem_batch_run(self._h, hs, ns, n)
+        else:
+            flat = np.zeros(max(n, 1) * self.k)
+            for i, a in enumerate(amps):
+                if a is not None:
+                    a = np.asarray(a, np.float64).reshape(-1)
+                    if a.size < int(nsteps[i]):
+                        raise ValueError("amplitudes shorter than the member's steps")
+                    flat[i * self.k:i * self.k + int(nsteps[i])] = a[:int(nsteps[i])]
+            rc = _batch_lib().lbem_batch_run_amp(self._h, hs, ns, flat.ctypes.data_as(C.POINTER(C.c_double)), n)
         if rc != 0:
             raise lbem.LbemError(rc, "lbem_batch_run")
 

@@ -425,6 +425,30 @@ def test_deviation_row_kernel_bitwise(shape, mu):
             assert got.shape == want.shape and np.array_equal(got, want), (prec, env)
 
 
+@pytest.mark.parametrize("shape,mu", [((64, 40, 20), True), ((100, 9, 7), False), ((512, 3, 4), False),
+                                      ((70, 1, 3), True), ((33, 17, 9), False), ((130, 5, 1), False),
+                                      ((200, 6, 5), True)])
+def test_whole_row_plain_kernel_bitwise(shape, mu):
+    """The 3D plain single step on whole-row blocks (x-moving populations
+    shifted through LDS, y/z ones read and pushed as aligned rows) leaves the
+    same state, bit for bit, as the cell-tile kernel: FP64, FP32 and plain
+    FP16 storage, pull and in-place AA (even and odd steps), sources spread
+    over many rows, mu, ragged and short rows, one-row and one-plane boxes."""
+    p = random_problem(3, shape, seed=sum(shape) + 61, mu=mu, nsteps=15)
+    cases = [("f64", "aa"), ("f64", "pull"), ("f32", "aa"), ("f32", "pull"), ("f16", "aa"), ("f16", "pull")]
+    for prec, st in cases:
+        env = {"LBEM_FUSE3": 1}
+        ref = gpu_run(p, 15, prec, st, env=dict(env, LBEM_XROW=0))
+        want = ref.get_state()
+        ref.close()
+        for nt in ("0", "1"):
+            announce(f"whole-row plain {shape} mu={mu} {prec} {st} NT={nt}")
+            s = gpu_run(p, 15, prec, st, env=dict(env, LBEM_XROW=1, LBEM_NT=nt))
+            got = s.get_state()
+            s.close()
+            assert got.shape == want.shape and np.array_equal(got, want), (prec, st, nt)
+
+
 def test_moments_on_device():
     import torch
     p = random_problem(3, (16, 12, 10), seed=5, nsteps=9)

@@ -66,11 +66,6 @@ def test_batch_rejects_unsupported_members():
     st = torch.cuda.Stream()
     b = serve.Batch(4, 5, st)
     p = random_problem(2, (32, 16, 1), seed=1, src=True, nsteps=4)
-    s = lbem.Solver(2, p.shape, "f32", streaming="pull", stream=st)
-    s.setup(p)                                  # has a current source
-    with pytest.raises(lbem.LbemError) as e:
-        b.run([s], [3])
-    assert e.value.code == lbem.LBEM_EINVAL
     s2 = lbem.Solver(2, p.shape, "f32", streaming="pull", stream=st)
     with pytest.raises(lbem.LbemError) as e:
         b.run([s2], [3])                        # not initialised
@@ -82,17 +77,69 @@ def test_batch_rejects_unsupported_members():
         b.run([s3, s3], [1, 1])                 # duplicate member
     with pytest.raises(lbem.LbemError):
         b.run([s3], [6])                        # more than steps_per_tick
-    s4 = lbem.Solver(2, q.shape, "f16ghost", streaming="pull", stream=st)
+    s4 = lbem.Solver(2, q.shape, "f32", streaming="pull", stream=st)
+    s4.set_boundary(0, "pec")
     s4.setup(q)
     with pytest.raises(lbem.LbemError) as e:
-        b.run([s4], [1])                        # no batched ghost-coordinate kernels
+        b.run([s4], [1])                        # walls: single-step kernels only
     assert e.value.code == lbem.LBEM_EINVAL
-    s5 = lbem.Solver(2, q.shape, "f16", streaming="aa", stream=st)
+    s5 = lbem.Solver(2, q.shape, "f32", streaming="pull", stream=st)
     s5.setup(q)
+    s5.set_absorber(np.full(q.n, 0.01))
     with pytest.raises(lbem.LbemError) as e:
-        b.run([s5], [1])                        # nor plain FP16 ones
+        b.run([s5], [1])                        # absorbing layer
     assert e.value.code == lbem.LBEM_EINVAL
     b.close()
+
+
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batch_with_sources_mu_and_every_format_bitwise(graph):
+    """Members with a current source (their amplitudes per step through
+    lbem_batch_run_amp), a non-uniform mu, the ghost-coordinate formats and
+    plain FP16 storage: each batched member equals the same lattice stepped
+    alone with the same amplitudes, bit for bit."""
+    import torch
+    os.environ["LBEM_BATCH_GRAPH"] = graph
+    try:
+        st = torch.cuda.Stream()
+        batch = serve.Batch(16, 6, st)
+    finally:
+        os.environ.pop("LBEM_BATCH_GRAPH", None)
+    cases = [(2, (64, 40, 1), "f32", "aa", True, False), (2, (48, 33, 1), "f64", "pull", True, True),
+             (2, (70, 24, 1), "f16ghost", "pull", True, False), (2, (40, 40, 1), "bf16ghost", "pull", False, True),
+             (2, (50, 30, 1), "f16", "aa", True, False), (3, (20, 12, 9), "f16ghost", "pull", True, True),
+             (3, (16, 16, 10), "f16dev", "pull", True, False), (3, (18, 11, 7), "f32", "pull", True, True),
+             (3, (12, 10, 8), "f16", "pull", True, False), (3, (14, 9, 6), "bf16dev", "pull", False, True)]
+    other = torch.cuda.Stream()
+    probs, solvers = [], []
+    total_steps = 17
+    for k, (dim, shape, prec, streaming, src, mu) in enumerate(cases):
+        p = random_problem(dim, shape, seed=300 + k, src=src, mu=mu, nsteps=total_steps)
+        s = lbem.Solver(dim, shape, prec, streaming=streaming, mu_varies=mu, stream=st if k % 2 else other)
+        s.setup(p)
+        probs.append(p)
+        solvers.append(s)
+    plan = [[6, 2, 6, 6, 0, 6, 3, 6, 6, 1], [6, 6, 5, 6, 6, 6, 6, 0, 6, 6], [5, 6, 6, 5, 6, 5, 6, 6, 5, 6]]
+    done = np.zeros(len(cases), int)
+    for ns in plan:
+        amps = [probs[k].amp[done[k]:done[k] + ns[k]] if cases[k][4] else None for k in range(len(cases))]
+        batch.run(solvers, ns, amps)
+        done += ns
+    for k, (dim, shape, prec, streaming, src, mu) in enumerate(cases):
+        announce(f"batch with extras graph={graph} {dim}d {shape} {prec} {streaming} src={src} mu={mu} "
+                 f"steps={done[k]}")
+        got = solvers[k].get_state()
+        p = probs[k]
+        ref = lbem.Solver(dim, shape, prec, streaming=streaming, mu_varies=mu)
+        ref.setup(p)
+        ref.step(int(done[k]), p.amp[:done[k]] if src else None)
+        want = ref.get_state()
+        ref.close()
+        assert solvers[k].t == done[k]
+        assert np.array_equal(got, want), (prec, streaming, src, mu)
+    for s in solvers:
+        s.close()
+    batch.close()
 
 
 def test_serving_mix_results_equal_solo_runs():
@@ -125,11 +172,12 @@ def test_batched_members_match_the_oracle():
     import torch
     from gpu_util import oracle_run, rel
     st = torch.cuda.Stream()
-    batch = serve.Batch(8, 9, st)
+    batch = serve.Batch(10, 9, st)
     rng = np.random.default_rng(77)
     cases = [(2, 96, "f64", "aa"), (2, 128, "f32", "pull"), (2, 80, "f16dev", "pull"),
-             (3, 24, "f32", "aa"), (3, 32, "f16dev", "pull"), (3, 20, "f64", "pull")]
-    tol = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3}
+             (3, 24, "f32", "aa"), (3, 32, "f16dev", "pull"), (3, 20, "f64", "pull"),
+             (2, 72, "f16ghost", "pull"), (3, 28, "f16ghost", "pull")]
+    tol = {"f64": 1e-12, "f32": 1e-5, "f16dev": 1e-3, "f16ghost": 1e-3}
     probs, solvers = [], []
     for dim, n, prec, streaming in cases:
         shp = (n, n) if dim == 2 else (n, n, n)
@@ -139,7 +187,7 @@ def test_batched_members_match_the_oracle():
         s.setup(p)
         probs.append(p)
         solvers.append(s)
-    plan = [[9, 9, 9, 9, 9, 9], [9, 4, 9, 9, 0, 9], [9, 9, 9, 5, 9, 9], [3, 9, 9, 9, 9, 9]]
+    plan = [[9, 9, 9, 9, 9, 9, 9, 9], [9, 4, 9, 9, 0, 9, 9, 2], [9, 9, 9, 5, 9, 9, 9, 9], [3, 9, 9, 9, 9, 9, 9, 9]]
     total = np.sum(plan, axis=0)
     for ns in plan:
         batch.run(solvers, ns)
@@ -152,4 +200,40 @@ def test_batched_members_match_the_oracle():
         assert eE <= tol[prec] and eB <= tol[prec], (prec, eE, eB)
     for s in solvers:
         s.close()
+    batch.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16ghost"])
+def test_batched_forced_member_matches_the_oracle(prec):
+    """The paper's forced problem inside a batch: the homogeneous test's
+    Gaussian current j_z (Subsection "Homogeneous media"), here with a
+    Ricker amplitude per step handed over through lbem_batch_run_amp, in a
+    heterogeneous medium with mu = 1 + (eps - 1)/3 (the B x grad ln mu source
+    term of the Maxwell section), against the FP64 oracle."""
+    import torch
+    from gpu_util import oracle_run, rel
+    n, K = 96, 8
+    rng = np.random.default_rng(5)
+    eps = 1.0 + 3.0 * inputs.smooth_noise(rng, (n, n), 10.0)
+    cells, w = inputs.paper_jz_source(n)
+    steps = 60
+    p = inputs.Problem(dim=2, shape=(n, n, 1), eps_r=eps.ravel(), mu_r=1.0 + (eps.ravel() - 1.0) / 3.0,
+                       E0=np.zeros((3, n * n)), B0=np.zeros((3, n * n)), src_comp=2, src_cells=cells,
+                       src_weights=w, amp=inputs.ricker(steps, 0.02), nsteps=steps)
+    st = torch.cuda.Stream()
+    batch = serve.Batch(4, K, st)
+    s = lbem.Solver(2, p.shape, prec, streaming="pull", mu_varies=True, stream=st)
+    s.setup(p)
+    done = 0
+    while done < steps:
+        k = min(K, steps - done)
+        batch.run([s], [k], [p.amp[done:done + k]])
+        done += k
+    Eg, Bg = s.moments()
+    Eo, Bo = oracle_run(p, steps).fields()
+    eE, eB = rel(Eg, Eo), rel(Bg, Bo)
+    announce(f"batched forced member {prec}: E {eE:.2e} B {eB:.2e}")
+    tol = 1e-5 if prec == "f32" else 1e-3
+    assert eE <= tol and eB <= tol, (eE, eB)
+    s.close()
     batch.close()
