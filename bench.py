@@ -306,8 +306,66 @@ def serving_run(rate: float, count: int) -> dict:
     return dict(requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
                 p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
                 mlups=rep.mlups, algorithmic_gbs=rep.algorithmic_gbs, ticks=rep.ticks,
+                gpu_busy_s=rep.gpu_busy_s, gpu_busy_frac=rep.gpu_busy_s / rep.wall_s if rep.wall_s > 0 else None,
                 mean_resident=rep.mean_resident, max_resident=rep.max_resident,
                 offered_mlups=sum(r.cells * r.nsteps for r in reqs) / reqs[-1].t_arrive / 1e6)
+
+
+def batch_classes(ticks: int = 10, warmup: int = 3, k: int = 50) -> list:
+    """Each batched class of the serving mix on its own: 20 resident lattices
+    of the mix's sizes (2D 64^2 - 1024^2 or 3D 32^3 - 128^3, four of each
+    side), one batch, `ticks` ticks of `k` steps event-timed on the batch
+    stream; beside it the same lattices stepped one by one with lbem_step."""
+    import torch
+    from paper_1108_2651_amd import inputs as I, lbem, serve as SV
+    rows = []
+    plan = [(2, "f32", "aa"), (2, "f16dev", "pull"), (3, "f32", "aa"), (3, "f16dev", "pull"),
+            (3, "f16ghost", "pull")]
+    for dim, prec, st in plan:
+        sides = (64, 128, 256, 512, 1024) if dim == 2 else (32, 48, 64, 96, 128)
+        rng = np.random.default_rng(11)
+        stream = torch.cuda.Stream()
+        solvers = []
+        for n in sides:
+            shp = (n, n) if dim == 2 else (n, n, n)
+            eps = 1.0 + 3.0 * I.smooth_noise(rng, shp, min(8.0, n / 8.0))
+            p = I.pulse_problem(dim, n, min(6.0, n / 6.0), rng, eps=eps)
+            for _ in range(4):
+                s = lbem.Solver(dim, p.shape, prec, streaming=st, stream=stream)
+                s.setup(p)
+                solvers.append(s)
+        cells = sum(s.n for s in solvers)
+        batch = SV.Batch(len(solvers), k, stream)
+        for _ in range(warmup):
+            batch.run(solvers, [k] * len(solvers))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(ticks):
+            batch.run(solvers, [k] * len(solvers))
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        batched = cells * k * ticks / (ms * 1e-3) / 1e6
+        # the same lattices one by one (their own kernels, single handles)
+        with torch.cuda.stream(stream):
+            for s in solvers[::4]:
+                s.step(k)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(stream)
+            for s in solvers:
+                s.step(k)
+            f1.record(stream)
+        f1.synchronize()
+        solo = cells * k / (f0.elapsed_time(f1) * 1e-3) / 1e6
+        row = dict(dim=dim, prec=prec, streaming=st, lattices=len(solvers), cells=cells, steps_per_tick=k,
+                   ms_per_tick=ms / ticks, batched_mlups=batched, solo_mlups=solo,
+                   batched_gbs=batched * bytes_per_cell(dim, prec) / 1e3)
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+        batch.close()
+        for s in solvers:
+            s.close()
+    return rows
 
 
 def load_traffic(name: str, kernel: str):
@@ -345,6 +403,8 @@ def main():
     ap.add_argument("--only", default=None, help="workload:prec[:streaming], e.g. c2:f32 or c3:f16dev")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="size sweep (one JSON line per point) instead")
+    ap.add_argument("--batch-classes", action="store_true",
+                    help="each batched serving class on its own, against the same lattices stepped alone")
     ap.add_argument("--oracle-table", action="store_true",
                     help="time the oracle at 1 thread and all cores on the small configurations instead")
     ap.add_argument("--serve-only", type=float, default=None, metavar="RATE",
@@ -372,6 +432,10 @@ def main():
 
     if args.sweep:
         size_sweep()
+        return
+
+    if args.batch_classes:
+        batch_classes()
         return
 
     if args.only:

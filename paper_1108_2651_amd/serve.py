@@ -128,6 +128,7 @@ class Report:
     mean_ms: float
     ticks: int
     mean_resident: float
+    gpu_busy_s: float        # sum of the ticks' event-timed durations on the batch stream (nan if not timed)
     max_resident: int
     latencies_ms: list = field(default_factory=list, repr=False)
 
@@ -290,6 +291,7 @@ class Scheduler:
                       p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                       mean_ms=float(lat.mean()), ticks=ticks,
                       mean_resident=resident_sum / max(ticks, 1), max_resident=resident_max,
+                      gpu_busy_s=float(ex.busy_seconds()) if hasattr(ex, "busy_seconds") else float("nan"),
                       latencies_ms=lat.tolist())
 
 
@@ -312,6 +314,7 @@ class GpuExecutor:
         self.local = threading.local()
         self.w0_vac = w0_vac
         self.problem_fn = problem_fn or request_problem_fast
+        self._tick_events = []
         self._bases = {}
         self._lock = threading.Lock()
 
@@ -357,7 +360,20 @@ class GpuExecutor:
         cf.wait(futs, return_when=cf.FIRST_COMPLETED, timeout=1.0)
 
     def tick(self, slots, nsteps):
+        # events around each tick on the batch stream; read once the run ends
+        torch = self.torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
         self.batch.run(slots, nsteps)
+        e1.record(self.stream)
+        self._tick_events.append((e0, e1))
+
+    def busy_seconds(self) -> float:
+        """Sum of the ticks' durations on the GPU (each from its first to its
+        last kernel, upload included).  Synchronises."""
+        self.torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in self._tick_events) * 1e-3
 
     def _finish(self, s, want):
         res = s.moments() if want else None

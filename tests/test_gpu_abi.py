@@ -73,3 +73,22 @@ def test_arena_and_streams():
     s2.step(10, p.amp[10:])
     a, b = s1.moments(), s2.moments()
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (1024, 8, 1)), (2, (2048, 4, 1)), (2, (600, 3, 1)),
+                                       (3, (600, 4, 3)), (3, (1024, 2, 2)), (3, (1030, 2, 2))])
+def test_rows_longer_than_the_row_kernels(dim, shape):
+    """Handles whose rows are longer than the whole-row kernels take (512
+    cells for the plain one, 1024 for the deviation one) are created, stepped
+    and read back in every format: their tilings fall back to the cell-tile
+    kernels."""
+    from gpu_util import random_problem
+    p = random_problem(dim, shape, seed=sum(shape), nsteps=3)
+    for prec in ("f64", "f32", "f16", "f16dev", "f16ghost"):
+        announce(f"long rows {dim}D {shape} {prec}")
+        s = lbem.Solver(dim, shape, prec, streaming="pull")
+        s.setup(p)
+        s.step(3, p.amp[:3])
+        E, B = s.moments()
+        assert np.isfinite(E).all() and np.isfinite(B).all()
+        s.close()

@@ -21,15 +21,25 @@ def _solo(p, prec, nsteps, streaming="pull"):
     return out
 
 
-@pytest.mark.parametrize("graph", ["1", "0"])
-def test_batch_matches_standalone_bitwise(graph):
+@pytest.mark.parametrize("graph,concurrent,group_mib", [("1", "0", "160"), ("0", "0", "160"), ("1", "1", "160"),
+                                                       ("0", "1", "160"), ("1", "0", "1"), ("1", "1", "1"),
+                                                       ("0", "0", "0")])
+def test_batch_matches_standalone_bitwise(graph, concurrent, group_mib):
+    """Classes of a tick run one after another on the batch stream (the
+    default) or concurrently on their own streams; graphs or direct launches;
+    members in groups that fit a state budget (1 MiB: one or two members per
+    group; 0: one group)."""
     import torch
     os.environ["LBEM_BATCH_GRAPH"] = graph
+    os.environ["LBEM_BATCH_CONCURRENT"] = concurrent
+    os.environ["LBEM_BATCH_GROUP_MIB"] = group_mib
     try:
         st = torch.cuda.Stream()
         batch = serve.Batch(16, 7, st)
     finally:
         os.environ.pop("LBEM_BATCH_GRAPH", None)
+        os.environ.pop("LBEM_BATCH_CONCURRENT", None)
+        os.environ.pop("LBEM_BATCH_GROUP_MIB", None)
     # plain members with pull or in-place AA storage (odd step counts leave AA
     # lattices in the swapped layout between ticks)
     cases = [(2, (96, 40, 1), "f32", "pull"), (2, (33, 17, 1), "f64", "pull"), (2, (130, 64, 1), "f16dev", "pull"),
@@ -51,7 +61,8 @@ def test_batch_matches_standalone_bitwise(graph):
     for ns in plan:
         batch.run(solvers, ns)
     for k, (dim, shape, prec, streaming) in enumerate(cases):
-        announce(f"batch vs solo graph={graph} {dim}d {shape} {prec} {streaming} steps={total[k]}")
+        announce(f"batch vs solo graph={graph} concurrent={concurrent} group={group_mib} {dim}d {shape} {prec} "
+                 f"{streaming} steps={total[k]}")
         got = solvers[k].moments()
         assert solvers[k].t == total[k]
         want = _solo(probs[k], prec, int(total[k]), streaming)
