@@ -195,6 +195,35 @@ static hipError_t follow_ticks(lbem_s* h)
     return hipStreamWaitEvent(h->stream, h->tick_ev, 0);
 }
 
+// Set-up staging buffers: stream-ordered allocations, whose release does not
+// wait for other streams' work (batch ticks in flight).  Buffers above 1 GiB
+// (lattices of 4e7 cells and more, never served in batches) and any request
+// the pool refuses use hipMalloc, whose hipFree synchronises the device: the
+// pool keeps freed memory until the next synchronisation, which must not hold
+// tens of GB beside a 2^30-cell lattice.
+struct Staging {
+    void* p = nullptr;
+    bool pooled = false;
+};
+static bool stage_alloc(Staging& st, size_t bytes, hipStream_t s)
+{
+    if (bytes <= (size_t(1) << 30) && hipMallocAsync(&st.p, bytes, s) == hipSuccess) {
+        st.pooled = true;
+        return true;
+    }
+    (void)hipGetLastError();
+    st.p = nullptr;
+    st.pooled = false;
+    return hipMalloc(&st.p, bytes) == hipSuccess;
+}
+static void stage_free(Staging& st, hipStream_t s)
+{
+    if (!st.p) return;
+    if (st.pooled) (void)hipFreeAsync(st.p, s);
+    else (void)hipFree(st.p);
+    st.p = nullptr;
+}
+
 #define HIP_OK(x)                                  \
     do {                                           \
         hipError_t e_ = (x);                       \
@@ -1274,21 +1303,18 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
     if (nonunit_mu && !h->cfg.mu_varies) return LBEM_EINVAL;
     API_SHARED;
     HIP_OK(follow_ticks(h));
-    // staging buffers are stream-ordered allocations: freeing them does not
-    // wait for other streams' work (batch ticks in flight)
-    double *deps = nullptr, *dmu = nullptr;
-    int* dflag = nullptr;
+    Staging s_eps, s_mu, s_flag;      // see stage_alloc
     int flag = 0, rc = LBEM_OK;
-    if (hipMallocAsync((void**)&deps, n * 8, h->stream) != hipSuccess) return LBEM_ENOMEM;
-    if (mu_r && hipMallocAsync((void**)&dmu, n * 8, h->stream) != hipSuccess) {
-        (void)hipFreeAsync(deps, h->stream);
+    if (!stage_alloc(s_eps, n * 8, h->stream) || (mu_r && !stage_alloc(s_mu, n * 8, h->stream)) ||
+        !stage_alloc(s_flag, sizeof(int), h->stream)) {
+        stage_free(s_eps, h->stream);
+        stage_free(s_mu, h->stream);
+        stage_free(s_flag, h->stream);
         return LBEM_ENOMEM;
     }
-    if (hipMallocAsync((void**)&dflag, sizeof(int), h->stream) != hipSuccess) {
-        (void)hipFreeAsync(deps, h->stream);
-        if (dmu) (void)hipFreeAsync(dmu, h->stream);
-        return LBEM_ENOMEM;
-    }
+    double* deps = (double*)s_eps.p;
+    double* dmu = (double*)s_mu.p;
+    int* dflag = (int*)s_flag.p;
     hipError_t e = hipMemcpyAsync(deps, eps_r, n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && mu_r) e = hipMemcpyAsync(dmu, mu_r, n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(dflag, 0, sizeof(int), h->stream);
@@ -1299,9 +1325,9 @@ int lbem_set_medium(lbem_t h, const double* eps_r, const double* mu_r)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = LBEM_EDEVICE;
     else if (flag) rc = LBEM_EUNSTABLE;
-    (void)hipFreeAsync(deps, h->stream);
-    if (dmu) (void)hipFreeAsync(dmu, h->stream);
-    (void)hipFreeAsync(dflag, h->stream);
+    stage_free(s_eps, h->stream);
+    stage_free(s_mu, h->stream);
+    stage_free(s_flag, h->stream);
     h->have_medium = rc == LBEM_OK;
     h->have_fields = false;
     return rc;
@@ -1320,19 +1346,21 @@ int lbem_init_fields(lbem_t h, const double* E, const double* B)
     }
     API_SHARED;
     HIP_OK(follow_ticks(h));
-    double *dE = nullptr, *dB = nullptr;      // stream-ordered staging (see lbem_set_medium)
-    if (hipMallocAsync((void**)&dE, 3 * n * 8, h->stream) != hipSuccess) return LBEM_ENOMEM;
-    if (hipMallocAsync((void**)&dB, 3 * n * 8, h->stream) != hipSuccess) {
-        (void)hipFreeAsync(dE, h->stream);
+    Staging s_E, s_B;                 // see stage_alloc
+    if (!stage_alloc(s_E, 3 * n * 8, h->stream) || !stage_alloc(s_B, 3 * n * 8, h->stream)) {
+        stage_free(s_E, h->stream);
+        stage_free(s_B, h->stream);
         return LBEM_ENOMEM;
     }
+    double* dE = (double*)s_E.p;
+    double* dB = (double*)s_B.p;
     hipError_t e = hipMemcpyAsync(dE, E, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dB, B, 3 * n * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = h->impl->init(h, dE, dB);
     if (e == hipSuccess && h->pol) e = hipMemsetAsync(h->pol, 0, pol_bytes(h), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFreeAsync(dE, h->stream);
-    (void)hipFreeAsync(dB, h->stream);
+    stage_free(s_E, h->stream);
+    stage_free(s_B, h->stream);
     if (e != hipSuccess) return LBEM_EDEVICE;
     h->t = 0;
     h->have_fields = true;

@@ -177,15 +177,26 @@ class Solver:
         self.close()
 
     # -- problem set-up -------------------------------------------------
+    def _setup_call(self, fn, *args, where=""):
+        """A set-up call stages host arrays through device buffers of its own;
+        if the device is out of memory because torch's caching allocator still
+        holds freed arenas, release them once and retry."""
+        rc = fn(self._h, *args)
+        if rc == LBEM_ENOMEM:
+            import torch
+            torch.cuda.empty_cache()
+            rc = fn(self._h, *args)
+        self._chk(rc, where)
+
     def set_medium(self, eps_r, mu_r=None):
         e = _f64(eps_r, self.n)
         m = None if mu_r is None else _f64(mu_r, self.n)
-        self._chk(load().lbem_set_medium(self._h, _ptr(e), _ptr(m)), "lbem_set_medium")
+        self._setup_call(load().lbem_set_medium, _ptr(e), _ptr(m), where="lbem_set_medium")
 
     def init_fields(self, E, B):
         e = _f64(E, 3 * self.n)
         b = _f64(B, 3 * self.n)
-        self._chk(load().lbem_init_fields(self._h, _ptr(e), _ptr(b)), "lbem_init_fields")
+        self._setup_call(load().lbem_init_fields, _ptr(e), _ptr(b), where="lbem_init_fields")
 
     def set_boundary(self, axis: int, kind: str):
         """Walls on both faces of ``axis``: 'pec', 'pmc' or 'periodic' (before

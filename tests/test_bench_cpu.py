@@ -2,6 +2,8 @@
 per-unit figures behind every roofline number) and of its contract on a
 machine without a GPU."""
 import json
+
+import pytest
 import subprocess
 import sys
 import os
@@ -55,12 +57,15 @@ def test_multi_gpu_request_exits_with_a_message():
 def test_kernel_hash_and_traffic_record():
     h = bench.kernel_source_hash()
     assert len(h) == 16
-    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_c2_2048_f32.json")))
-    # the record names the kernel and carries the calibration it was scaled by
-    assert rec["kernel"].startswith("k_step_fused2d<float,2,8")
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_c4_512_f16ghost.json")))
+    # the record names the headline kernel and carries the calibration it was scaled by
+    assert rec["kernel"] == bench.PRIMARY_KERNEL
     assert 1.99 < rec["fetch_scale"] < 2.01 and rec["write_scale"] == 1.0
-    assert rec["algorithmic_bytes_per_launch"] == 44 * 2048 * 2048
-    assert bench.load_traffic("c2_2048_f32", "another kernel") is None
+    assert rec["algorithmic_bytes_per_launch"] == 112 * 512 ** 3
+    assert rec["bytes_per_launch"] == pytest.approx(
+        rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"] + rec["write_kib_per_dispatch"] * 1024 *
+        rec["write_scale"])
+    assert bench.load_traffic("c4_512_f16ghost", "another kernel") is None
 
 
 def test_symbols_of_the_binding_match_the_header():

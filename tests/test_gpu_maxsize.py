@@ -47,12 +47,16 @@ def pulses(shape, centres, comp):
 
 
 def sampled(p, prec, k, samples, tol):
+    import torch
+    torch.cuda.empty_cache()          # arenas of earlier tests, cached by torch
     s = lbem.Solver(p.dim, p.shape, prec, w0_vac=p.w0_vac)
     s.setup(p)
     spl = s.steps_per_launch
     s.step(k)
     Eg, Bg = s.moments()
     s.close()
+    del s
+    torch.cuda.empty_cache()
     nx, ny, nz = p.shape
     worst = 0.0
     for centre in samples:
