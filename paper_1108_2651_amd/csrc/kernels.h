@@ -1580,8 +1580,12 @@ __device__ __forceinline__ void row_pops_of(const float* Min, const H* Din, int6
 // NTS: streaming stores of the state.  src_*: per (block, plane of the chunk)
 // a range [off[b*lz + rel], off[b*lz + rel + 1]) of (row*nx + x, pair) entries
 // with their value per unit amplitude.
+// At least four waves per SIMD (<= 128 VGPRs): two 512-thread blocks per CU.
+// With fewer, one block holds a CU and the latency of its loads between the
+// barriers of a plane has nothing to hide it (measured 3.19 -> 4.38 ms at
+// 512^3 when a change took the kernel to 141 VGPRs).
 template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
-__global__ __launch_bounds__(NTB) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
+__global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
                                                    const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                    const RowGeo g, const int* __restrict__ soff,
                                                    const int2* __restrict__ sent, const float* __restrict__ sval,

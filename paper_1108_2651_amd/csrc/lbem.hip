@@ -837,11 +837,16 @@ static void make_row_geo(lbem_s* h)
     g.tpr = tpr;
     g.ty = ntb / tpr;
     g.tiles_y = (ny + g.ty - 1) / g.ty;
-    int lz = 32;
+    // Measured (512^3 and 256^3, FP16 ghost and Dev-Q): blocks dealt to the
+    // XCDs round-robin, so that the blocks resident at a time are neighbouring
+    // tiles of one z band, run 5-7 % faster than contiguous tile ranges per XCD
+    // (512^3 ghost 2.97 against 3.20 ms); chunks of 8 planes 0.3-1 % faster
+    // than 16 or 32.
+    int lz = 8;
     while (lz > 1 && (int64_t)g.tiles_y * ((nz + lz - 1) / lz) < 1024) lz /= 2;
     g.lz = std::max(1, env_int("LBEM_DEV3R_LZ", lz));
     g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
-    g.xcd = env_int("LBEM_DEV3R_XCD", 1);
+    g.xcd = env_int("LBEM_DEV3R_XCD", 0);
 }
 
 // inverse of tile_coords()
