@@ -20,6 +20,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <type_traits>
 
 #include "lattice.h"
@@ -1584,20 +1585,30 @@ __device__ __forceinline__ void row_pops_of(const float* Min, const H* Din, int6
 // With fewer, one block holds a CU and the latency of its loads between the
 // barriers of a plane has nothing to hide it (measured 3.19 -> 4.38 ms at
 // 512^3 when a change took the kernel to 141 VGPRs).
+// One tile (block b of the tiling g) of the row-tile step; every thread of the
+// block calls it (it holds barriers).  lp: 12 * CX * NTB floats, lh: 6 * RX
+// floats of LDS.
+template <int CX, int NTB>
+struct RowLds {
+    static constexpr int ROWC_MAX = CX * NTB;       // cells of one plane of the tile (ty * nx <= CX * NTB)
+    static constexpr int RX = CX * NTB < ROWX_MAX ? CX * NTB : ROWX_MAX;   // longest row of this block size
+    static constexpr int FLOATS = 12 * ROWC_MAX + 6 * RX;
+};
+
 template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
-__global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
-                                                   const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
-                                                   const RowGeo g, const int* __restrict__ soff,
-                                                   const int2* __restrict__ sent, const float* __restrict__ sval,
-                                                   const float amp, const float omega, const int tau_half)
+__device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float* Mout, H* Dout,
+                                           const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                           const RowGeo& g, const int b, const int* __restrict__ soff,
+                                           const int2* __restrict__ sent, const float* __restrict__ sval,
+                                           const float amp, const float omega, const int tau_half, float* lp,
+                                           float* lh)
 {
     constexpr int D = 3, Q = 7, P = 3, NM = P + D, NC = DevSlots<D, GH>::N;
-    constexpr int ROWC_MAX = CX * NTB;       // cells of one plane of the tile (ty * nx <= CX * NTB)
-    constexpr int RX = CX * NTB < ROWX_MAX ? CX * NTB : ROWX_MAX;   // longest row of this block size
-    __shared__ float lp[12 * ROWC_MAX];      // [j*3 + p][row*nx + x]: in-plane outgoing populations
-    __shared__ float lh[6 * RX];             // [side*3 + p][x]: +y of row y0-1 (side 0), -y of row y0+rows (side 1)
+    constexpr int ROWC_MAX = RowLds<CX, NTB>::ROWC_MAX;
+    constexpr int RX = RowLds<CX, NTB>::RX;
+    // lp: [j*3 + p][row*nx + x], the in-plane outgoing populations; lh:
+    // [side*3 + p][x], +y of row y0-1 (side 0) and -y of row y0+rows (side 1)
 
-    const int b = remap_block(blockIdx.x, g.nblocks, g.xcd);
     const int tyi = b % g.tiles_y, zc = b / g.tiles_y;
     const int y0 = tyi * g.ty, z0 = zc * g.lz;
     const int z1 = min(z0 + g.lz, g.nz);
@@ -1781,6 +1792,19 @@ __global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H
         }
         __syncthreads();
     }
+}
+
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
+__global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
+                                                   const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
+                                                   const RowGeo g, const int* __restrict__ soff,
+                                                   const int2* __restrict__ sent, const float* __restrict__ sval,
+                                                   const float amp, const float omega, const int tau_half)
+{
+    __shared__ float lds[RowLds<CX, NTB>::FLOATS];
+    dev3r_tile<H, GH, MU, NTS, CX, NTB>(Min, Din, Mout, Dout, cl2a, dlnmu, g,
+                                        remap_block(blockIdx.x, g.nblocks, g.xcd), soff, sent, sval, amp, omega,
+                                        tau_half, lds, lds + 12 * RowLds<CX, NTB>::ROWC_MAX);
 }
 
 // ---------------------------------------------------------------------------
@@ -2079,7 +2103,9 @@ __global__ __launch_bounds__(NT) void k_step_dev3f(const float* Min, const H* Di
 // numbered by the prefix tile_base; a persistent grid strides over them.  The
 // per-cell code is the same inline code as the single-lattice kernels, so a
 // lattice advanced here is bit-identical to the same lattice stepped alone.
-// Lattices carry no current source and mu == 1 (the serving workload).
+// Members may carry a current source (amplitudes per step of the tick) and a
+// varying mu; cell extras (walls, absorber, dispersion, anisotropy) are not
+// batched.
 struct BatchGrid {
     void* buf[2];        // plain: population copies; dev: moment arrays
     void* dev[2];        // dev: deviation arrays (unused for plain)
@@ -2098,19 +2124,41 @@ struct BatchGrid {
     int tile_base;       // first work item of this lattice
     int aa;              // plain formats stored in place (AA pattern); fresh then
                          // means the natural (even-step) layout at the tick start
+    int row;             // 3D deviation member that also has the whole-row tiling
+                         // rgeo (work items row_base.., source table rsrc_*)
+    int row_base;
+    RowGeo rgeo;
+    const int* rsrc_off;
+    const int2* rsrc_ent;
+    const float* rsrc_val;
 };
+
+// A pointer read from the descriptor table, as a global-memory pointer.  The
+// table holds generic pointers; read as such, every access through them
+// compiles to a flat instruction, which also counts against the LDS counter,
+// so each LDS wait of a tile waits for its outstanding HBM loads as well
+// (measured: the whole-row batched tile 1.8x slower than the same tile in a
+// single-lattice launch, whose pointers are kernel arguments).
+template <typename T>
+__device__ __forceinline__ T* gmem(const void* p)
+{
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
 
 struct BatchHdr {
     int count;           // lattices in the table
-    int total_tiles;
+    int total_tiles;     // work items of the per-cell tiles
+    int total_rows;      // work items of the whole-row tiles (all members row)
 };
 
+// the member that owns work item w (ROWS: of the whole-row numbering)
+template <bool ROWS = false>
 __device__ __forceinline__ int batch_find(const BatchGrid* __restrict__ tab, int count, int w)
 {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].tile_base <= w) lo = mid;
+        if ((ROWS ? tab[mid].row_base : tab[mid].tile_base) <= w) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -2122,10 +2170,10 @@ template <int P, typename T>
 __device__ __forceinline__ bool batch_source(const BatchGrid& G, int tile, int k, T* lds)
 {
     SrcArgs<T> s;
-    s.off = G.src_off;
-    s.ent = G.src_ent;
-    s.val = (const T*)G.src_val;
-    s.amp = G.amp ? ((const T*)G.amp)[k] : T(0);
+    s.off = G.src_off ? gmem<const int>(G.src_off) : nullptr;
+    s.ent = gmem<const int2>(G.src_ent);
+    s.val = gmem<const T>(G.src_val);
+    s.amp = G.amp ? gmem<const T>(G.amp)[k] : T(0);
     return stage_source<P, 1, T>(s, tile, lds);
 }
 
@@ -2144,8 +2192,8 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
     const bool mu = G.dlnmu != nullptr;
     if (x >= g.nx || y >= g.ny) return;
     const int s = G.aa ? 0 : (G.cur0 + k) & 1;
-    const S* src = (const S*)G.buf[s];
-    S* dst = (S*)G.buf[G.aa ? 0 : s ^ 1];     // AA: in place, each location read and written by one thread
+    const S* src = gmem<const S>(G.buf[s]);
+    S* dst = gmem<S>(G.buf[G.aa ? 0 : s ^ 1]);     // AA: in place, each location read and written by one thread
     const Cell C = make_cell(g, x, y, z);
     T f[Q][P];
 #pragma unroll
@@ -2153,7 +2201,7 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
 #pragma unroll
         for (int p = 0; p < P; ++p)
             f[i][p] = ld_pop<T>(src[(int64_t)(read_slot<D, RM>(i) * P + p) * g.n + read_cell<D, RM>(C, i)]);
-    const T cl2 = ((const T*)G.cl2)[C.c];
+    const T cl2 = gmem<const T>(G.cl2)[C.c];
     T rho[P], K[D], Sp[P];
     moments<D, T>(f, rho, K);
 #pragma unroll
@@ -2161,7 +2209,7 @@ __device__ __forceinline__ void batch_tile_plain(const BatchGrid& G, int tile, i
     if (mu) {
         T dl[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) dl[a] = ((const T*)G.dlnmu)[(int64_t)a * g.n + C.c];
+        for (int a = 0; a < D; ++a) dl[a] = gmem<const T>(G.dlnmu)[(int64_t)a * g.n + C.c];
         add_mu_source<D, T>(K, cl2, dl, Sp);
     }
     T out[Q][P];
@@ -2187,12 +2235,12 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
     const bool mu = G.dlnmu != nullptr;
     if (x >= g.nx || y >= g.ny) return;
     const int s = (G.cur0 + k) & 1;
-    const float* Min = (const float*)G.buf[s];
-    const H* Din = (const H*)G.dev[s];
-    float* Mout = (float*)G.buf[s ^ 1];
-    H* Dout = (H*)G.dev[s ^ 1];
+    const float* Min = gmem<const float>(G.buf[s]);
+    const H* Din = gmem<const H>(G.dev[s]);
+    float* Mout = gmem<float>(G.buf[s ^ 1]);
+    H* Dout = gmem<H>(G.dev[s ^ 1]);
     const Cell C = make_cell(g, x, y, z);
-    const float cl2 = ((const float*)G.cl2)[C.c];
+    const float cl2 = gmem<const float>(G.cl2)[C.c];
     const float wc0 = 1.f / cl2 - float(D);
     float f[Q][P];
 #pragma unroll
@@ -2207,7 +2255,7 @@ __device__ __forceinline__ void batch_tile_dev(const BatchGrid& G, int tile, int
     if (mu) {
         float dl[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) dl[a] = ((const float*)G.dlnmu)[(int64_t)a * g.n + C.c];
+        for (int a = 0; a < D; ++a) dl[a] = gmem<const float>(G.dlnmu)[(int64_t)a * g.n + C.c];
         add_mu_source<D, float>(K, cl2, dl, Sp);
     }
     dev_collide_store<D, H, GH>(f, cl2, wc0, Sp, has_src || mu, (float)G.omega, G.tau_half != 0, rho, K, g.n,
@@ -2251,6 +2299,37 @@ __global__ __launch_bounds__(NT) void k_step_batch_dev(const BatchHdr* __restric
         if (G.fresh && k == 0) batch_tile_dev<D, H, GH, R_LOCAL>(G, w - G.tile_base, k, lds);
         else batch_tile_dev<D, H, GH, R_PULL>(G, w - G.tile_base, k, lds);
         __syncthreads();   // the next work item may stage its source into lds
+    }
+}
+
+// 3D deviation members on the whole-row tiling (rows of up to 2 NT cells):
+// the row-tile step, work items numbered by row_base (the member's RowGeo
+// blocks).  A tick launches it for steps after its first when every member of
+// the class is on that tiling and all or none of them have a varying mu (MU);
+// otherwise, and for the first step (which may start from the natural layout),
+// the per-cell kernel above.  This kernel holds nothing but the row tile: with
+// the per-cell paths or a run-time mu branch in the same kernel the compiler
+// issues the code loads of a plane one at a time (measured 1.8x slower).
+template <typename H, bool GH, bool MU>
+__global__ __launch_bounds__(NT, 4) void k_step_batch_dev3_rows(const BatchHdr* __restrict__ hdr,
+                                                             const BatchGrid* __restrict__ tab, int k)
+{
+    constexpr int CX = 2;
+    using L = RowLds<CX, NT>;
+    __shared__ float lds[L::FLOATS];
+    const int count = hdr->count, total = hdr->total_rows;
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int gi = batch_find<true>(tab, count, w);
+        const BatchGrid& G = tab[gi];
+        if (k >= G.nsteps) continue;
+        const int s = (G.cur0 + k) & 1;
+        const RowGeo rg = G.rgeo;       // held in registers: the tile's stores cannot alias it
+        dev3r_tile<H, GH, MU, false, CX, NT>(
+            gmem<const float>(G.buf[s]), gmem<const H>(G.dev[s]), gmem<float>(G.buf[s ^ 1]), gmem<H>(G.dev[s ^ 1]),
+            gmem<const float>(G.cl2), MU ? gmem<const float>(G.dlnmu) : nullptr, rg, w - G.row_base,
+            G.rsrc_off ? gmem<const int>(G.rsrc_off) : nullptr, gmem<const int2>(G.rsrc_ent),
+            gmem<const float>(G.rsrc_val), G.amp ? gmem<const float>(G.amp)[k] : 0.f, (float)G.omega, G.tau_half,
+            lds, lds + 12 * L::ROWC_MAX);
     }
 }
 

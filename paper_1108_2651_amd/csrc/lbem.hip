@@ -166,6 +166,14 @@ struct lbem_s {
     int2* rsrc_ent;
     float* rsrc_val;
     int64_t nrsrc;
+    // the whole-row tiling of this handle inside a batch (3D deviation formats,
+    // rows of up to 2 NT cells; 256-thread blocks) and its source table
+    int brow;
+    RowGeo bgeo;
+    int* bsrc_off;
+    int2* bsrc_ent;
+    float* bsrc_val;
+    int64_t nbsrc;
     // state
     // non-periodic faces and absorbing layer
     int bc_kind[3];
@@ -849,6 +857,25 @@ static void make_row_geo(lbem_s* h)
     g.xcd = env_int("LBEM_DEV3R_XCD", 0);
 }
 
+// The whole-row tiling of a 3D deviation handle inside a batch: 256-thread
+// blocks (the batched kernel's), two cells per thread and ceil(nx/2) threads
+// per row, so short rows fill the block (nx = 32: 16 rows per tile); chunks of
+// 8 planes.  Rows longer than 2 NT cells keep the per-cell tiles.
+static void make_batch_row_geo(lbem_s* h)
+{
+    const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
+    h->brow = (h->D == 3 && is_dev(h->prec) && nx <= 2 * NT) ? env_int("LBEM_BATCH_ROW", 1) : 0;
+    if (!h->brow) return;
+    RowGeo& g = h->bgeo;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
+    g.tpr = (nx + 1) / 2;
+    g.ty = NT / g.tpr;
+    g.tiles_y = (ny + g.ty - 1) / g.ty;
+    g.lz = std::max(1, env_int("LBEM_BATCH_ROW_LZ", 8));
+    g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
+    g.xcd = 0;
+}
+
 // inverse of tile_coords()
 static int tile_id(const Geo& g, int tx, int ty, int z)
 {
@@ -994,6 +1021,7 @@ int lbem_create(const lbem_config* cfg, lbem_t* out)
     make_zmarch_geo(h);
     make_row_geo(h);
     make_xrow_geo(h);
+    make_batch_row_geo(h);
     // Measured: streaming loads/stores slow a launch whose state fits the
     // 256 MB Infinity Cache (by up to 1.8x) and speed it up beyond that: in 3D
     // from about 1.5 times the cache on (2-10 %; at 344 MB still 9 % slower),
@@ -1046,6 +1074,11 @@ static void free_source(lbem_s* h)
     h->zsrc_off = nullptr; h->zsrc_ent = nullptr; h->zsrc_val = nullptr;
     h->rsrc_off = nullptr; h->rsrc_ent = nullptr; h->rsrc_val = nullptr;
     h->nrsrc = 0;
+    if (h->bsrc_off) (void)hipFree(h->bsrc_off);
+    if (h->bsrc_ent) (void)hipFree(h->bsrc_ent);
+    if (h->bsrc_val) (void)hipFree(h->bsrc_val);
+    h->bsrc_off = nullptr; h->bsrc_ent = nullptr; h->bsrc_val = nullptr;
+    h->nbsrc = 0;
     h->nsrc = 0;
     h->nfsrc = 0;
     h->nzsrc = 0;
@@ -1146,11 +1179,11 @@ static int build_zmarch_source(lbem_s* h, const std::vector<std::pair<int64_t, d
     return LBEM_OK;
 }
 
-// Source entries of the whole-row tiling: per (block, plane of its chunk) the
+// Source entries of a whole-row tiling g: per (block, plane of its chunk) the
 // cells (row * nx + x) that carry a current, with S per unit amplitude.
-static int build_row_source(lbem_s* h, const std::vector<std::pair<int64_t, double>>& cells, int pp)
+static int build_row_source(const RowGeo& g, const std::vector<std::pair<int64_t, double>>& cells, int pp,
+                            int** off_out, int2** ent_out, float** val_out, int64_t* count)
 {
-    const RowGeo& g = h->rgeo;
     struct Item { int64_t key; int local; float v; };
     std::vector<Item> items;
     items.reserve(cells.size());
@@ -1173,15 +1206,15 @@ static int build_row_source(lbem_s* h, const std::vector<std::pair<int64_t, doub
         val[k] = items[k].v;
     }
     const size_t ms = items.size();
-    if (hipMalloc((void**)&h->rsrc_off, off.size() * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&h->rsrc_ent, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
-        hipMalloc((void**)&h->rsrc_val, std::max<size_t>(ms, 1) * sizeof(float)) != hipSuccess)
+    if (hipMalloc((void**)off_out, off.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)ent_out, std::max<size_t>(ms, 1) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)val_out, std::max<size_t>(ms, 1) * sizeof(float)) != hipSuccess)
         return LBEM_ENOMEM;
-    hipError_t e = hipMemcpy(h->rsrc_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && ms) e = hipMemcpy(h->rsrc_ent, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
-    if (e == hipSuccess && ms) e = hipMemcpy(h->rsrc_val, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(*off_out, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(*ent_out, ent.data(), ms * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && ms) e = hipMemcpy(*val_out, val.data(), ms * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) return LBEM_EDEVICE;
-    h->nrsrc = (int64_t)ms;
+    *count = (int64_t)ms;
     return LBEM_OK;
 }
 
@@ -1589,11 +1622,14 @@ int lbem_set_source(lbem_t h, int comp, const int64_t* cells, const double* weig
     }
     if (e != hipSuccess) { free_source(h); return LBEM_EDEVICE; }
     h->nsrc = (int64_t)ms;
-    if (h->zmarch) {
+    if (h->zmarch || h->brow) {
         std::vector<std::pair<int64_t, double>> cv(merged.size());
         for (size_t k = 0; k < merged.size(); ++k) cv[k] = {merged[k].first, src_value[k]};
-        int rc = build_zmarch_source(h, cv, pp);
-        if (rc == LBEM_OK && h->rowk) rc = build_row_source(h, cv, pp);
+        int rc = h->zmarch ? build_zmarch_source(h, cv, pp) : LBEM_OK;
+        if (rc == LBEM_OK && h->zmarch && h->rowk)
+            rc = build_row_source(h->rgeo, cv, pp, &h->rsrc_off, &h->rsrc_ent, &h->rsrc_val, &h->nrsrc);
+        if (rc == LBEM_OK && h->brow)
+            rc = build_row_source(h->bgeo, cv, pp, &h->bsrc_off, &h->bsrc_ent, &h->bsrc_val, &h->nbsrc);
         if (rc != LBEM_OK) { free_source(h); return rc; }
     }
     if (h->xrow) {
@@ -1809,6 +1845,11 @@ namespace {
 constexpr int NPREC = 7;   // LBEM_F64 .. LBEM_F16
 constexpr int NCLASS = 2 * NPREC;  // (dim - 2) * NPREC + prec
 constexpr int BATCH_BLOCKS = 8192;  // persistent grid (more blocks than fit: the rest start as others finish)
+// How a class's steps after the first of a tick run: the per-cell kernel, or
+// (3D deviation classes whose members all have the whole-row tiling) the
+// row-tile kernel with mu == 1 or with varying mu
+constexpr int NMODE = 3;
+enum { MODE_CELL = 0, MODE_ROWS = 1, MODE_ROWS_MU = 2 };
 
 int class_of(const lbem_s* h) { return (h->D - 2) * NPREC + h->prec; }
 
@@ -1826,12 +1867,14 @@ struct lbem_batch_s {
     hipEvent_t ev[NRING];      // each slot is free again once its upload has executed
     int ring;
     size_t group_bytes;        // members of one call run in groups touching at most this much state per step
-    // one graph per class: ksteps launches of that class's kernel, captured
-    // and instantiated once, in lbem_batch_create
-    hipGraph_t graph[NCLASS];
-    hipGraphExec_t exec[NCLASS];
+    // per class and mode one graph of ksteps launches, captured and
+    // instantiated once, in lbem_batch_create (the row modes of the 3D
+    // deviation classes only)
+    hipGraph_t graph[NCLASS][NMODE];
+    hipGraphExec_t exec[NCLASS][NMODE];
     int use_graph;
     int blocks;                // persistent grid of each class launch
+    int rows_min;              // fewest whole-row work items for the row modes
     // the classes of a tick run concurrently, one stream each (default
     // priority), forked from the batch stream after the table upload and
     // joined back before anything later on it
@@ -1840,36 +1883,54 @@ struct lbem_batch_s {
     int concurrent;
 };
 
+// the first step of a tick always takes the per-cell kernel: it reads
+// members that start from the natural layout
+template <int D, typename H, bool GH>
+static void launch_batch_dev(dim3 g, dim3 t, hipStream_t st, const BatchHdr* hdr, const BatchGrid* tab, int k,
+                             int mode)
+{
+    if constexpr (D == 3) {
+        if (k > 0 && mode == MODE_ROWS) {
+            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, false>), g, t, 0, st, hdr, tab, k);
+            return;
+        }
+        if (k > 0 && mode == MODE_ROWS_MU) {
+            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, true>), g, t, 0, st, hdr, tab, k);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_step_batch_dev<D, H, GH>), g, t, 0, st, hdr, tab, k);
+}
+
 template <int D>
 static void launch_class_d(lbem_batch_s* b, int prec, const BatchHdr* hdr, const BatchGrid* tab, int k,
-                           hipStream_t st)
+                           hipStream_t st, int mode)
 {
     dim3 g(b->blocks), t(NT);
     switch (prec) {
         case LBEM_F64: hipLaunchKernelGGL((k_step_batch_plain<D, double>), g, t, 0, st, hdr, tab, k); break;
         case LBEM_F32: hipLaunchKernelGGL((k_step_batch_plain<D, float>), g, t, 0, st, hdr, tab, k); break;
-        case LBEM_F16DEV: hipLaunchKernelGGL((k_step_batch_dev<D, __half, false>), g, t, 0, st, hdr, tab, k); break;
-        case LBEM_BF16DEV:
-            hipLaunchKernelGGL((k_step_batch_dev<D, __hip_bfloat16, false>), g, t, 0, st, hdr, tab, k);
-            break;
-        case LBEM_F16GHOST: hipLaunchKernelGGL((k_step_batch_dev<D, __half, true>), g, t, 0, st, hdr, tab, k); break;
-        case LBEM_BF16GHOST:
-            hipLaunchKernelGGL((k_step_batch_dev<D, __hip_bfloat16, true>), g, t, 0, st, hdr, tab, k);
-            break;
+        case LBEM_F16DEV: launch_batch_dev<D, __half, false>(g, t, st, hdr, tab, k, mode); break;
+        case LBEM_BF16DEV: launch_batch_dev<D, __hip_bfloat16, false>(g, t, st, hdr, tab, k, mode); break;
+        case LBEM_F16GHOST: launch_batch_dev<D, __half, true>(g, t, st, hdr, tab, k, mode); break;
+        case LBEM_BF16GHOST: launch_batch_dev<D, __hip_bfloat16, true>(g, t, st, hdr, tab, k, mode); break;
         default:
             hipLaunchKernelGGL((k_step_batch_plain<D, float, __half>), g, t, 0, st, hdr, tab, k);
             break;
     }
 }
 
-static void launch_class(lbem_batch_s* b, int c, int k, hipStream_t st)
+static void launch_class(lbem_batch_s* b, int c, int k, hipStream_t st, int mode)
 {
     const size_t cb = class_bytes(b->max_grids);
     const BatchHdr* hdr = (const BatchHdr*)(b->dev + c * cb);
     const BatchGrid* tab = (const BatchGrid*)(b->dev + c * cb + align256(sizeof(BatchHdr)));
-    if (c < NPREC) launch_class_d<2>(b, c, hdr, tab, k, st);
-    else launch_class_d<3>(b, c - NPREC, hdr, tab, k, st);
+    if (c < NPREC) launch_class_d<2>(b, c, hdr, tab, k, st, mode);
+    else launch_class_d<3>(b, c - NPREC, hdr, tab, k, st, mode);
 }
+
+// classes that have the row modes: 3D deviation formats
+static bool has_row_modes(int c) { return c >= NPREC && is_dev(c - NPREC); }
 
 // Capture the per-class graphs.  Done once, at creation, with the library
 // lock held exclusively: no graph is ever captured or instantiated while
@@ -1878,26 +1939,28 @@ static bool capture_classes(lbem_batch_s* b)
 {
     std::unique_lock<std::shared_mutex> lk(g_api_mu);
     for (int c = 0; c < NCLASS; ++c) {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k, b->stream);
-            e = hipStreamEndCapture(b->stream, &graph);
+        for (int mode = 0; mode < (has_row_modes(c) ? NMODE : 1); ++mode) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k, b->stream, mode);
+                e = hipStreamEndCapture(b->stream, &graph);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                return false;
+            }
+            b->graph[c][mode] = graph;
+            b->exec[c][mode] = exec;
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            return false;
-        }
-        b->graph[c] = graph;
-        b->exec[c] = exec;
     }
     return true;
 }
 
-static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
+static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask, const int* mode)
 {
     const bool conc = b->concurrent && (mask & (mask - 1)) != 0;   // two classes or more
     hipError_t e = hipSuccess;
@@ -1910,9 +1973,9 @@ static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
             if ((e = hipStreamWaitEvent(st, b->fork_ev, 0)) != hipSuccess) return e;
         }
         if (b->use_graph) {
-            if ((e = hipGraphLaunch(b->exec[c], st)) != hipSuccess) return e;
+            if ((e = hipGraphLaunch(b->exec[c][mode[c]], st)) != hipSuccess) return e;
         } else {
-            for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k, st);
+            for (int k = 0; k < b->ksteps; ++k) launch_class(b, c, k, st, mode[c]);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (conc) {
@@ -1925,12 +1988,13 @@ static hipError_t enqueue_tick(lbem_batch_s* b, unsigned mask)
 
 static void release_graphs(lbem_batch_s* b)
 {
-    for (int c = 0; c < NCLASS; ++c) {
-        if (b->exec[c]) (void)hipGraphExecDestroy(b->exec[c]);
-        if (b->graph[c]) (void)hipGraphDestroy(b->graph[c]);
-        b->exec[c] = nullptr;
-        b->graph[c] = nullptr;
-    }
+    for (int c = 0; c < NCLASS; ++c)
+        for (int mode = 0; mode < NMODE; ++mode) {
+            if (b->exec[c][mode]) (void)hipGraphExecDestroy(b->exec[c][mode]);
+            if (b->graph[c][mode]) (void)hipGraphDestroy(b->graph[c][mode]);
+            b->exec[c][mode] = nullptr;
+            b->graph[c][mode] = nullptr;
+        }
 }
 
 // State bytes one step of a member reads or writes: its population copies
@@ -1950,7 +2014,8 @@ static int enqueue_group(lbem_batch_s* b, const lbem_t* handles, const int64_t* 
     if (hipEventSynchronize(b->ev[b->ring]) != hipSuccess) return LBEM_EDEVICE;
     char* host = b->pinned[b->ring];
     const size_t cb = class_bytes(b->max_grids);
-    int cnt[NCLASS] = {0}, tiles[NCLASS] = {0};
+    int cnt[NCLASS] = {0}, tiles[NCLASS] = {0}, rows[NCLASS] = {0};
+    int nrow[NCLASS] = {0}, nmu[NCLASS] = {0};
     unsigned mask = 0;
     size_t amp_used = 0;      // end of the amplitudes written for this group
     for (int q = 0; q < m; ++q) {
@@ -1971,9 +2036,22 @@ static int enqueue_group(lbem_batch_s* b, const lbem_t* handles, const int64_t* 
             G.buf[1] = h->pop[1];
             G.dev[0] = h->pop[0] + moff;
             G.dev[1] = h->pop[1] + moff;
+            if (h->brow) {
+                G.row = 1;
+                G.row_base = rows[c];
+                rows[c] += h->bgeo.nblocks;
+                nrow[c]++;
+                G.rgeo = h->bgeo;
+                if (h->nbsrc) {
+                    G.rsrc_off = h->bsrc_off;
+                    G.rsrc_ent = h->bsrc_ent;
+                    G.rsrc_val = h->bsrc_val;
+                }
+            }
         }
         G.cl2 = h->cl2;
         G.dlnmu = h->mu_set ? h->dlnmu : nullptr;
+        nmu[c] += h->mu_set ? 1 : 0;
         // the member's own tiling, so that its per-tile source table applies
         Geo& g = G.geo;
         g = h->geo;
@@ -2004,10 +2082,17 @@ static int enqueue_group(lbem_batch_s* b, const lbem_t* handles, const int64_t* 
         tiles[c] += g.nblocks;
         mask |= 1u << c;
     }
+    int mode[NCLASS];
     for (int c = 0; c < NCLASS; ++c) {
         BatchHdr* hd = (BatchHdr*)(host + c * cb);
         hd->count = cnt[c];
         hd->total_tiles = tiles[c];
+        hd->total_rows = rows[c];
+        mode[c] = MODE_CELL;
+        if (has_row_modes(c) && cnt[c] > 0 && nrow[c] == cnt[c] && rows[c] >= b->rows_min) {
+            if (nmu[c] == 0) mode[c] = MODE_ROWS;
+            else if (nmu[c] == cnt[c]) mode[c] = MODE_ROWS_MU;
+        }
     }
     // members set up on other streams: their work so far precedes the group
     for (int q = 0; q < m; ++q) {
@@ -2022,7 +2107,7 @@ static int enqueue_group(lbem_batch_s* b, const lbem_t* handles, const int64_t* 
         return LBEM_EDEVICE;
     if (hipEventRecord(b->ev[b->ring], b->stream) != hipSuccess) return LBEM_EDEVICE;
     b->ring = (b->ring + 1) % NRING;
-    if (mask && enqueue_tick(b, mask) != hipSuccess) return LBEM_EDEVICE;
+    if (mask && enqueue_tick(b, mask, mode) != hipSuccess) return LBEM_EDEVICE;
     // ... and later work on a member's own stream (moments, destroy) follows
     // it: the member's stream waits on this event at its next use (follow_ticks)
     for (int q = 0; q < m; ++q) {
@@ -2050,6 +2135,14 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     b->ring = 0;
     b->use_graph = env_int("LBEM_BATCH_GRAPH", 1);
     b->blocks = std::max(1, env_int("LBEM_BATCH_BLOCKS", BATCH_BLOCKS));
+    // A row work item is a chunk of planes of a whole-row tile: 8-16 times a
+    // per-cell tile.  Measured (FP16-dev): 20 lattices of 128^3 (10240 items)
+    // 35.2k MLUPS with row tiles against 29.9k per-cell; 20 of 64^3 (1280
+    // items) 27.0k against 33.0k; the serving mix at 200 req/s, whose 3D
+    // classes hold a few small lattices, 37.2 against 38.6 GLUPS with the row
+    // tiles always on (100 req/s: p50 141 against 62 ms).  So a class takes
+    // them only with enough items to fill the GPU several times over.
+    b->rows_min = std::max(0, env_int("LBEM_BATCH_ROWS_MIN", 3072));
     b->amp_off = class_bytes(max_lattices) * NCLASS;
     const size_t bytes = b->amp_off + align256((size_t)max_lattices * steps_per_tick * 8);
     b->dev = nullptr;
@@ -2067,8 +2160,10 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     // 38.9 GLUPS at 200 req/s.  So it is off unless LBEM_BATCH_GROUP_MIB is set.
     b->group_bytes = (size_t)std::max(0, env_int("LBEM_BATCH_GROUP_MIB", 0)) << 20;
     for (int c = 0; c < NCLASS; ++c) {
-        b->graph[c] = nullptr;
-        b->exec[c] = nullptr;
+        for (int mode = 0; mode < NMODE; ++mode) {
+            b->graph[c][mode] = nullptr;
+            b->exec[c][mode] = nullptr;
+        }
         b->cstream[c] = nullptr;
         b->join_ev[c] = nullptr;
     }

@@ -153,6 +153,73 @@ def test_batch_with_sources_mu_and_every_format_bitwise(graph):
     batch.close()
 
 
+# Members of the 3D deviation classes for the whole-row batched tiles: (shape,
+# format, source, varying mu).  "rows": every class all on the row tiling with
+# mu == 1; "rows_mu": all with varying mu; "cells": classes that fall back to
+# the per-cell tiles (a row longer than 2 NT cells, mixed mu).
+ROW_SETS = {
+    "rows": [((32, 32, 12), "f16dev", False, False), ((9, 30, 10), "f16dev", True, False),
+             ((33, 7, 5), "f16dev", True, False), ((128, 9, 1), "f16ghost", False, False),
+             ((512, 2, 3), "f16ghost", True, False), ((40, 1, 12), "f16ghost", True, False),
+             ((96, 20, 17), "bf16dev", True, False), ((17, 5, 9), "bf16ghost", False, False)],
+    "rows_mu": [((24, 10, 9), "f16dev", True, True), ((33, 7, 5), "f16ghost", True, True),
+                ((64, 3, 3), "bf16ghost", False, True), ((20, 12, 9), "f16ghost", False, True)],
+    "cells": [((520, 3, 4), "f16dev", True, True), ((32, 8, 8), "f16dev", False, False),
+              ((20, 12, 9), "f16ghost", True, True), ((16, 16, 10), "f16ghost", True, False)],
+}
+
+
+@pytest.mark.parametrize("which", list(ROW_SETS))
+def test_batched_row_tiles_bitwise(which):
+    """3D deviation members on the batch's whole-row tiling (two cells per
+    thread, ceil(nx/2) threads per row), with the row kernel forced on for
+    every class that qualifies: short, odd and single rows, tiles taller than
+    the box, one plane, chunks longer than the box, rows of exactly 2 NT cells;
+    first steps from the natural layout, members that ran solo steps before
+    they joined, sources and mu; and classes that fall back to the per-cell
+    tiles.  Each member equals its solo run bit for bit."""
+    import torch
+    st = torch.cuda.Stream()
+    os.environ["LBEM_BATCH_ROWS_MIN"] = "0"
+    try:
+        batch = serve.Batch(16, 6, st)
+    finally:
+        os.environ.pop("LBEM_BATCH_ROWS_MIN", None)
+    cases = ROW_SETS[which]
+    pre = [3 if k % 3 == 2 else 0 for k in range(len(cases))]      # solo steps before joining the batch
+    plan = [[6, 5, 6, 6, 0, 6, 1, 6][:len(cases)], [6, 6, 6, 3, 6, 6, 6, 0][:len(cases)],
+            [2, 6, 0, 6, 6, 4, 6, 6][:len(cases)]]
+    total_steps = max(pre) + sum(max(r) for r in plan)
+    probs, solvers = [], []
+    for k, (shape, prec, src, mu) in enumerate(cases):
+        p = random_problem(3, shape, seed=500 + k, src=src, mu=mu, nsteps=total_steps)
+        s = lbem.Solver(3, shape, prec, mu_varies=mu, stream=st)
+        s.setup(p)
+        if pre[k]:
+            s.step(pre[k], p.amp[:pre[k]] if src else None)
+        probs.append(p)
+        solvers.append(s)
+    done = np.array(pre)
+    for ns in plan:
+        amps = [probs[k].amp[done[k]:done[k] + ns[k]] if cases[k][2] else None for k in range(len(cases))]
+        batch.run(solvers, ns, amps)
+        done += ns
+    for k, (shape, prec, src, mu) in enumerate(cases):
+        announce(f"batched row tiles [{which}] {shape} {prec} src={src} mu={mu} steps={done[k]}")
+        got = solvers[k].get_state()
+        p = probs[k]
+        ref = lbem.Solver(3, shape, prec, mu_varies=mu)
+        ref.setup(p)
+        ref.step(int(done[k]), p.amp[:done[k]] if src else None)
+        want = ref.get_state()
+        ref.close()
+        assert solvers[k].t == done[k]
+        assert np.array_equal(got, want), (shape, prec, src, mu)
+    for s in solvers:
+        s.close()
+    batch.close()
+
+
 def test_serving_mix_results_equal_solo_runs():
     reqs = serve.make_requests(count=20, rate=400.0, seed=11, steps_lo=30, steps_hi=160,
                                side2d=(5, 7.5), side3d=(4, 5.5))
