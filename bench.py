@@ -71,11 +71,12 @@ def extra_bytes(p, prec: str) -> int:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device code and its compiler flags (the launch shape is
-    checked separately, by the kernel name recorded with the counters)."""
+    """Hash of the device code, the host code that picks its launch geometry
+    (tiling, block order) and the compiler flags; the kernel instantiation is
+    checked separately, by the kernel name recorded with the counters."""
     h = hashlib.sha256()
     for f in ("paper_1108_2651_amd/csrc/kernels.h", "paper_1108_2651_amd/csrc/lattice.h",
-              "paper_1108_2651_amd/build.py"):
+              "paper_1108_2651_amd/csrc/lbem.hip", "paper_1108_2651_amd/build.py"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -181,9 +181,19 @@ __device__ __forceinline__ int write_slot(int i)
 
 __device__ __forceinline__ int remap_block(int bid, int nb, int on)
 {
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-    // contiguous range of tiles so that neighbouring rows share its L2.
-    if (on && (nb & 7) == 0) return (bid & 7) * (nb >> 3) + (bid >> 3);
+    // Workgroups are dealt round-robin to the 8 XCDs.  on == 1: give each XCD
+    // one contiguous range of tiles, so that neighbouring tiles share its L2.
+    // on = G >= 2: deal runs of G consecutive tiles to each XCD in turn (the
+    // blocks resident at a time stay one band of neighbouring tiles, and the
+    // G tiles of a run share one L2); the last nb mod 8G tiles keep their ids.
+    if (on == 1) return (nb & 7) == 0 ? (bid & 7) * (nb >> 3) + (bid >> 3) : bid;
+    if (on >= 2) {
+        const int full = nb - nb % (8 * on);
+        if (bid < full) {
+            const int x = bid & 7, j = bid >> 3;
+            return ((j / on) * 8 + x) * on + j % on;
+        }
+    }
     return bid;
 }
 

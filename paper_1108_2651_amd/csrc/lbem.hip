@@ -846,15 +846,17 @@ static void make_row_geo(lbem_s* h)
     g.ty = ntb / tpr;
     g.tiles_y = (ny + g.ty - 1) / g.ty;
     // Measured (512^3 and 256^3, FP16 ghost and Dev-Q): blocks dealt to the
-    // XCDs round-robin, so that the blocks resident at a time are neighbouring
+    // XCDs in turn, so that the blocks resident at a time are neighbouring
     // tiles of one z band, run 5-7 % faster than contiguous tile ranges per XCD
-    // (512^3 ghost 2.97 against 3.20 ms); chunks of 8 planes 0.3-1 % faster
+    // (512^3 ghost 2.95 against 3.20 ms); runs of 8 neighbouring tiles per XCD
+    // (their y-halo rows shared in one L2) another 0.8-1.2 % (2.92 ms; runs
+    // of 2, 4 or 16 within 0.5 % of it); chunks of 8 planes 0.3-1 % faster
     // than 16 or 32.
     int lz = 8;
     while (lz > 1 && (int64_t)g.tiles_y * ((nz + lz - 1) / lz) < 1024) lz /= 2;
     g.lz = std::max(1, env_int("LBEM_DEV3R_LZ", lz));
     g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
-    g.xcd = env_int("LBEM_DEV3R_XCD", 0);
+    g.xcd = env_int("LBEM_DEV3R_XCD", 8);
 }
 
 // The whole-row tiling of a 3D deviation handle inside a batch: 256-thread
