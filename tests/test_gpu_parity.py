@@ -154,7 +154,8 @@ def test_temporal_blocking_3d_bitwise(prec, shape, mu):
     p = random_problem(3, shape, seed=sum(shape) + 13, mu=mu, nsteps=31)
     ref = gpu_run(p, 31, prec, "pull", env={"LBEM_FUSE3": 1}).moments()
     combos = [dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=32), dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=3),
-              dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=1)]
+              dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=1),
+              dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=3)]
     for env in combos:
         env["LBEM_FUSE3"] = 2
         announce(f"fused3d {prec} {shape} {env}")
@@ -323,6 +324,8 @@ def test_aa_pull_and_tilings_bitwise(dim):
     if dim == 3:
         variants.append(dict(streaming="pull", env={"LBEM_STRIP": 3}))
         variants.append(dict(streaming="aa", env={"LBEM_STRIP": 2, "LBEM_XCD": 0}))
+        variants.append(dict(streaming="aa", env={"LBEM_XCD": 3}))
+        variants.append(dict(streaming="pull", env={"LBEM_XCD": 5, "LBEM_FUSE3": 1}))
     if dim == 2:
         variants.append(dict(streaming="pull", env={"LBEM_VEC": 1}))
         variants.append(dict(streaming="aa", env={"LBEM_VEC": 4}))
