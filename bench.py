@@ -295,14 +295,15 @@ def size_sweep(steps: int = 100, warmup: int = 5) -> list:
 
 
 SERVING_CONFIG = ("Poisson arrivals; 70% 2D 64^2-1024^2, 30% 3D 32^3-128^3; smooth eps in [1,4]; "
-                  "200-2000 steps; half FP32, half FP16-dev; 2 GiB device budget; 100 steps per tick; "
-                  "latency = arrival to E,B on the host")
+                  "200-2000 steps; half FP32, half FP16-dev (the *_f16ghost row: FP16 ghost coordinates); "
+                  "2 GiB device budget; 100 steps per tick; latency = arrival to E,B on the host")
 
 
-def serving_run(rate: float, count: int) -> dict:
-    """The continuous-batching serving mix at `rate` requests/s."""
+def serving_run(rate: float, count: int, lowp_prec: str = "f16dev") -> dict:
+    """The continuous-batching serving mix at `rate` requests/s (its 16-bit
+    requests in `lowp_prec`)."""
     from paper_1108_2651_amd import serve as SV
-    reqs = SV.make_requests(count=count, rate=rate)
+    reqs = SV.make_requests(count=count, rate=rate, lowp_prec=lowp_prec)
     rep = SV.serve(reqs, budget_bytes=2 << 30, max_slots=256, steps_per_tick=100, workers=10)
     return dict(requests=len(reqs), completed=rep.completed, rejected=rep.rejected,
                 p50_ms=rep.p50_ms, p99_ms=rep.p99_ms, mean_ms=rep.mean_ms, wall_s=rep.wall_s,
@@ -401,6 +402,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-lowp", default="f16dev", help="format of the mix's 16-bit requests")
     ap.add_argument("--only", default=None, help="workload:prec[:streaming], e.g. c2:f32 or c3:f16dev")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="size sweep (one JSON line per point) instead")
@@ -447,7 +449,7 @@ def main():
         return
 
     if args.serve_only is not None:
-        print(json.dumps(serving_run(args.serve_only, args.serve_requests)), flush=True)
+        print(json.dumps(serving_run(args.serve_only, args.serve_requests, args.serve_lowp)), flush=True)
         return
 
     print(f"[bench] primary: config4 512^3 {PRIMARY_PREC}", file=sys.stderr, flush=True)
@@ -486,6 +488,9 @@ def main():
         for rate in (200.0, 100.0):
             print(f"[bench] serving mix at {rate:.0f} req/s", file=sys.stderr, flush=True)
             serving[f"{rate:.0f}_req_per_s"] = serving_run(rate, args.serve_requests)
+        # the same requests with the 16-bit ones in ghost coordinates
+        print("[bench] serving mix at 200 req/s, FP16 ghost", file=sys.stderr, flush=True)
+        serving["200_req_per_s_f16ghost"] = serving_run(200.0, args.serve_requests, "f16ghost")
         serving["config"] = SERVING_CONFIG
 
     cpu = None

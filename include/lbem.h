@@ -315,10 +315,13 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
  * dispersion, anisotropy), created with pull streaming (or AA for the plain
  * formats LBEM_F64, LBEM_F32, LBEM_F16), any format (EINVAL otherwise).  A
  * member's current source runs at amplitude 0 here (as lbem_step with
- * amp == NULL); lbem_batch_run_amp gives the amplitudes.  Returns once
- * enqueued; lbem_moments on a member synchronises.  The host-side table is
- * double-buffered: a call waits only for the upload of the tick before the
- * previous one. */
+ * amp == NULL); lbem_batch_run_amp gives the amplitudes.  The members of a
+ * 3D class run in groups whose state touched per step fits a cache-sized
+ * budget (environment LBEM_BATCH_GROUP_MIB, default 224 MiB; 0 turns it off),
+ * each group for all its steps; the results are the same bits either way.
+ * Returns once enqueued; lbem_moments on a member synchronises.  Each group's
+ * table is uploaded through one of eight pinned staging slots: a call waits
+ * only when a slot's previous upload has not executed yet. */
 int lbem_batch_run(lbem_batch_t b, const lbem_t* handles, const int64_t* nsteps, int count);
 
 /* lbem_batch_run with source amplitudes: amp (host, count * steps_per_tick

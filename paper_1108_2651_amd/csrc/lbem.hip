@@ -2158,13 +2158,14 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     }
     // Lattices small enough for the 256 MB Infinity Cache are served from it
     // when several steps run on them back to back: with a budget, a tick runs
-    // its members in groups whose state a step touches fits it, each group
-    // for all of its steps, instead of every member once per step.  Measured
-    // per class (20 lattices of the serving sizes, 160 MiB): 3D FP32 AA 28.3k
-    // -> 37.0k MLUPS, 3D FP16 ghost 28.5k -> 37.5k, 2D FP32 134k -> 126k; on
-    // the serving mix, whose work sits in its largest lattices, 37.9 against
-    // 38.9 GLUPS at 200 req/s.  So it is off unless LBEM_BATCH_GROUP_MIB is set.
-    b->group_bytes = (size_t)std::max(0, env_int("LBEM_BATCH_GROUP_MIB", 0)) << 20;
+    // the members of each 3D class in groups whose state a step touches fits
+    // it, each group for all of its steps, instead of every member once per
+    // step.  Measured on the serving mix at 200 req/s: 38.7 GLUPS without
+    // groups; 41.8, 43.4, 44.3-44.4, 44.0, 41.6 and 38.8 with 96, 160, 224,
+    // 256, 320 and 640 MiB (100 req/s at 224 MiB: p50 68 ms, p99 0.37 s).
+    // Groups that mixed classes (each group replaying every class's graph)
+    // had measured 37.9.  LBEM_BATCH_GROUP_MIB=0 turns grouping off.
+    b->group_bytes = (size_t)std::max(0, env_int("LBEM_BATCH_GROUP_MIB", 224)) << 20;
     for (int c = 0; c < NCLASS; ++c) {
         for (int mode = 0; mode < NMODE; ++mode) {
             b->graph[c][mode] = nullptr;
@@ -2250,19 +2251,30 @@ int lbem_batch_run_amp(lbem_batch_t b, const lbem_t* handles, const int64_t* nst
         for (int j = 0; j < i; ++j)
             if (handles[j] == h) return LBEM_EINVAL;
     }
-    // groups of consecutive members whose state touched per step fits the
-    // budget (a member larger than the budget runs in a group of its own)
+    // With a budget, members run in groups, each for all its steps: the
+    // members of one class in call order, a 3D class split into runs of
+    // members whose state touched per step fits the budget (a member larger
+    // than it runs alone), a 2D class in one group.  Without one, all members
+    // form one group.
     std::vector<int> order;
     order.reserve(count);
     for (int i = 0; i < count; ++i)
         if (nsteps[i] > 0) order.push_back(i);
+    if (b->group_bytes)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return class_of(handles[x]) < class_of(handles[y]); });
     size_t g0 = 0;
     while (g0 < order.size()) {
         size_t g1 = g0, used = 0;
+        const int c0 = class_of(handles[order[g0]]);
         while (g1 < order.size()) {
-            const size_t t = touched_bytes(handles[order[g1]]);
-            if (g1 > g0 && b->group_bytes && used + t > b->group_bytes) break;
-            used += t;
+            const lbem_s* h = handles[order[g1]];
+            if (b->group_bytes) {
+                if (class_of(h) != c0) break;
+                const size_t t = touched_bytes(h);
+                if (g1 > g0 && h->D == 3 && used + t > b->group_bytes) break;
+                used += t;
+            }
             ++g1;
         }
         const int rc = enqueue_group(b, handles, nsteps, amp, order.data() + g0, (int)(g1 - g0));

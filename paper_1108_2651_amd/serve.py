@@ -417,13 +417,15 @@ def request_problem_fast(r: Request, ex):
                    nsteps=r.nsteps, w0_vac=ex.w0_vac, name=f"req{r.rid}")
 
 
-def make_requests(count: int = 2000, rate: float = 200.0, seed: int | None = None, **kw):
-    """The serving mix as Request objects (Poisson arrivals)."""
+def make_requests(count: int = 2000, rate: float = 200.0, seed: int | None = None, lowp_prec: str = "f16dev",
+                  **kw):
+    """The serving mix as Request objects (Poisson arrivals); the requests for
+    16-bit storage take `lowp_prec` (FP16 deviations by default)."""
     from .inputs import serving_requests
     out = []
     for k, d in enumerate(serving_requests(count, rate, seed, **kw)):
         out.append(Request(rid=k, t_arrive=d["t_arrive"], dim=d["dim"], n=d["n"], nsteps=d["nsteps"],
-                           prec="f16dev" if d["lowp"] else "f32", seed=d["seed"]))
+                           prec=lowp_prec if d["lowp"] else "f32", seed=d["seed"]))
     return out
 
 
