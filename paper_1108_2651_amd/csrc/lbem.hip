@@ -854,9 +854,11 @@ static void make_row_geo(lbem_s* h)
     // tiles of one z band, run 5-7 % faster than contiguous tile ranges per XCD
     // (512^3 ghost 2.95 against 3.20 ms); runs of 8 neighbouring tiles per XCD
     // (their y-halo rows shared in one L2) another 0.8-1.2 % (2.92 ms; runs
-    // of 2, 4 or 16 within 0.5 % of it); chunks of 8 planes 0.3-1 % faster
-    // than 16 or 32.
-    int lz = 8;
+    // of 2, 4 or 16 within 0.5 % of it).  Chunks of 7 planes: 512^3 ghost
+    // 2.909-2.913 ms against 2.917-2.925 with 8 (16: 2.945), 256^3 ghost
+    // 0.366 against 0.379 ms, Dev-Q 0.438 against 0.448 (5 planes is 1 %
+    // faster at 256^3 and 0.7 % slower at 512^3).
+    int lz = 7;
     while (lz > 1 && (int64_t)g.tiles_y * ((nz + lz - 1) / lz) < 1024) lz /= 2;
     g.lz = std::max(1, env_int("LBEM_DEV3R_LZ", lz));
     g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
