@@ -70,14 +70,25 @@ def extra_bytes(p, prec: str) -> int:
     return extra
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank lines (a comment edit leaves
+    the compiled code, and so a counter record, valid)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
     """Hash of the device code, the host code that picks its launch geometry
-    (tiling, block order) and the compiler flags; the kernel instantiation is
-    checked separately, by the kernel name recorded with the counters."""
+    (tiling, block order) and the compiler flags, comments left out; the kernel
+    instantiation is checked separately, by the kernel name recorded with the
+    counters."""
     h = hashlib.sha256()
     for f in ("paper_1108_2651_amd/csrc/kernels.h", "paper_1108_2651_amd/csrc/lattice.h",
-              "paper_1108_2651_amd/csrc/lbem.hip", "paper_1108_2651_amd/build.py"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+              "paper_1108_2651_amd/csrc/lbem.hip"):
+        h.update(_code_only(open(os.path.join(ROOT, f), encoding="utf-8").read()).encode())
+    h.update(open(os.path.join(ROOT, "paper_1108_2651_amd/build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 
