@@ -1605,13 +1605,17 @@ struct RowLds {
     static constexpr int FLOATS = 12 * ROWC_MAX + 6 * RX;
 };
 
-template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
+// EXT: the cell extras that leave the streaming alone -- the dispersion pole
+// (ade_update before the collision, J/c^2 added to the rest particle after
+// it) and the absorbing layer (the outgoing state scaled by 1 - sigma) -- as
+// the per-cell kernel applies them; no walls, no anisotropy.
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, bool EXT = false>
 __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float* Mout, H* Dout,
                                            const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                            const RowGeo& g, const int b, const int* __restrict__ soff,
                                            const int2* __restrict__ sent, const float* __restrict__ sval,
                                            const float amp, const float omega, const int tau_half, float* lp,
-                                           float* lh)
+                                           float* lh, const CellExt& bc = CellExt{})
 {
     constexpr int D = 3, Q = 7, P = 3, NM = P + D, NC = DevSlots<D, GH>::N;
     constexpr int ROWC_MAX = RowLds<CX, NTB>::ROWC_MAX;
@@ -1786,8 +1790,28 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
                 for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * n + c];
                 add_mu_source<D, float>(K, cl2, dl, Sp);
             }
-            dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, n, (int)c,
-                                             Mout, Dout);
+            if constexpr (!EXT) {
+                dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, n,
+                                                 (int)c, Mout, Dout);
+            } else {
+                float Jn[P];
+                const bool ade = bc.ade != nullptr;
+                if (ade) ade_update<D, float>(bc, n, (int)c, cl2, rho, Jn);
+                float out[Q][P];
+                collide<D, float>(f, cl2, Sp, any_src, omega, tau_half != 0, rho, K, out);
+                if (ade) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) out[0][p] += Jn[p] / cl2;
+                }
+                if (bc.keep) {
+                    const float kp = ((const float*)bc.keep)[c];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+#pragma unroll
+                        for (int p = 0; p < P; ++p) out[i][p] *= kp;
+                }
+                dev_store<D, H, GH, NTS>(out, cl2, wc0, n, (int)c, Mout, Dout);
+            }
         }
         // the march moves on one plane
 #pragma unroll
@@ -1804,17 +1828,18 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
     }
 }
 
-template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB>
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, bool EXT = false>
 __global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
                                                    const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                    const RowGeo g, const int* __restrict__ soff,
                                                    const int2* __restrict__ sent, const float* __restrict__ sval,
-                                                   const float amp, const float omega, const int tau_half)
+                                                   const float amp, const float omega, const int tau_half,
+                                                   const CellExt bc)
 {
     __shared__ float lds[RowLds<CX, NTB>::FLOATS];
-    dev3r_tile<H, GH, MU, NTS, CX, NTB>(Min, Din, Mout, Dout, cl2a, dlnmu, g,
-                                        remap_block(blockIdx.x, g.nblocks, g.xcd), soff, sent, sval, amp, omega,
-                                        tau_half, lds, lds + 12 * RowLds<CX, NTB>::ROWC_MAX);
+    dev3r_tile<H, GH, MU, NTS, CX, NTB, EXT>(Min, Din, Mout, Dout, cl2a, dlnmu, g,
+                                             remap_block(blockIdx.x, g.nblocks, g.xcd), soff, sent, sval, amp,
+                                             omega, tau_half, lds, lds + 12 * RowLds<CX, NTB>::ROWC_MAX, bc);
 }
 
 // ---------------------------------------------------------------------------

@@ -534,12 +534,18 @@ struct DevImpl : Impl {
         const int P = Lat<D>::P;
         return (H*)(h->pop[k] + align256((size_t)(P + D) * h->n * 4));
     }
-    template <bool MU, bool NTS, int NTB>
+    template <bool MU, bool NTS, int NTB, bool EXT = false>
     static void go_row_n(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
     {
-        hipLaunchKernelGGL((k_step_dev3r<H, GH, MU, NTS, 2, NTB>), dim3(h->rgeo.nblocks), dim3(NTB), 0, h->stream,
-                           M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
-                           (const float*)h->dlnmu, h->rgeo, so, h->rsrc_ent, h->rsrc_val, amp, om, th);
+        hipLaunchKernelGGL((k_step_dev3r<H, GH, MU, NTS, 2, NTB, EXT>), dim3(h->rgeo.nblocks), dim3(NTB), 0,
+                           h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
+                           (const float*)h->dlnmu, h->rgeo, so, h->rsrc_ent, h->rsrc_val, amp, om, th, ext_of(h));
+    }
+    // the row-tile step with the extras that leave the streaming alone
+    // (dispersion, absorbing layer): 512-thread tiles, no walls, no anisotropy
+    static bool row_ext_ok(const lbem_s* h)
+    {
+        return h->rowk && !ext_of(h).walls() && !h->ra_set && h->rgeo.tpr * h->rgeo.ty == 512;
     }
     template <bool MU>
     static hipError_t go_row(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
@@ -564,6 +570,16 @@ struct DevImpl : Impl {
     static hipError_t go(lbem_s* h, int from, int to, float amp)
     {
         SrcArgs<float> s;
+        if constexpr (D == 3 && BX && RM == R_PULL) {
+            if (row_ext_ok(h)) {
+                const int* so = h->nrsrc ? h->rsrc_off : nullptr;
+                const float om = (float)(1.0 / h->cfg.tau);
+                const int th = h->cfg.tau == 0.5;
+                if (h->nts) go_row_n<MU, true, 512, true>(h, from, to, so, amp, om, th);
+                else go_row_n<MU, false, 512, true>(h, from, to, so, amp, om, th);
+                return hipGetLastError();
+            }
+        }
         if constexpr (D == 3 && !BX && RM == R_PULL) {
             if (h->rowk) {
                 const int* so = h->nrsrc ? h->rsrc_off : nullptr;

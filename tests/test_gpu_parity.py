@@ -429,6 +429,44 @@ def test_deviation_row_kernel_bitwise(shape, mu):
             assert got.shape == want.shape and np.array_equal(got, want), (prec, env)
 
 
+@pytest.mark.parametrize("shape,mu", [((64, 40, 20), True), ((100, 9, 7), False), ((33, 17, 37), False),
+                                      ((128, 6, 1), True), ((300, 4, 6), False)])
+def test_row_kernel_with_extras_bitwise(shape, mu):
+    """The row-tile step with the extras that leave the streaming alone -- the
+    dispersion pole (auxiliary fields updated in place) and the absorbing
+    layer -- leaves the same state, bit for bit, as the per-cell kernel with
+    the same extras: every 16-bit format, each extra alone and both, sources,
+    mu, ragged rows and tiles, one-plane boxes."""
+    from paper_1108_2651_amd import lbem
+    steps = 19
+    p = random_problem(3, shape, seed=sum(shape) + 71, mu=mu, nsteps=steps)
+    rng = np.random.default_rng(sum(shape) + 72)
+    wp2, w02, gam = rng.uniform(0, 0.02, p.n), rng.uniform(0, 0.03, p.n), rng.uniform(0, 0.01, p.n)
+    sigma = np.where(rng.random(p.n) < 0.3, rng.uniform(0, 0.05, p.n), 0.0)
+    for prec in LOWP:
+        for extras in ("dispersion", "absorber", "both"):
+            states = []
+            for row in ("0", "1"):
+                os.environ.update(LBEM_DEV3Z="1", LBEM_DEV3R=row)
+                try:
+                    s = lbem.Solver(3, shape, prec, mu_varies=mu)
+                finally:
+                    os.environ.pop("LBEM_DEV3Z", None)
+                    os.environ.pop("LBEM_DEV3R", None)
+                s.set_medium(p.eps_r, p.mu_r)
+                if extras != "dispersion":
+                    s.set_absorber(sigma)
+                if extras != "absorber":
+                    s.set_dispersion(wp2, w02, gam)
+                s.init_fields(p.E0, p.B0)
+                s.set_source(p.src_comp, p.src_cells, p.src_weights)
+                s.step(steps, p.amp[:steps])
+                states.append(s.get_state())
+                s.close()
+            announce(f"row kernel with extras {shape} mu={mu} {prec} {extras}")
+            assert states[0].shape == states[1].shape and np.array_equal(states[0], states[1]), (prec, extras)
+
+
 @pytest.mark.parametrize("shape,mu", [((64, 40, 20), True), ((100, 9, 7), False), ((512, 3, 4), False),
                                       ((70, 1, 3), True), ((33, 17, 9), False), ((130, 5, 1), False),
                                       ((200, 6, 5), True)])
