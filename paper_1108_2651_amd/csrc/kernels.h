@@ -1297,8 +1297,10 @@ __device__ __forceinline__ void dev_collide_store(const float (&f)[Lat<D>::Q][La
     for (int sl = 0; sl < DevSlots<D, GH>::N; ++sl) st_stream<NTS>(&Dout[(int64_t)sl * n + c], code[sl]);
 }
 
-// NTS: streaming stores of the state (the gathered loads stay plain)
-template <int D, typename H, bool GH, int RM, int VEC, bool MU, bool BX, bool NTS = false>
+// NTS: streaming stores of the state (the gathered loads stay plain).  BX:
+// 0 no cell extras; 1 walls only (they change the arrivals, not the
+// collision, which keeps its closed form); 2 walls, dispersion and absorber.
+template <int D, typename H, bool GH, int RM, int VEC, bool MU, int BX, bool NTS = false>
 __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din, float* Mout, H* Dout,
                                                 const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                 const Geo g, const SrcArgs<float> s, const float omega,
@@ -1339,7 +1341,7 @@ __global__ __launch_bounds__(NT) void k_step_dev(const float* Min, const H* Din,
             for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * g.n + C.c];
             add_mu_source<D, float>(K, cl2, dl, Sp);
         }
-        if constexpr (!BX) {
+        if constexpr (BX <= 1) {
             dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, g.n, C.c,
                                              Mout, Dout);
         } else {
@@ -1605,11 +1607,16 @@ struct RowLds {
     static constexpr int FLOATS = 12 * ROWC_MAX + 6 * RX;
 };
 
-// EXT: the cell extras that leave the streaming alone -- the dispersion pole
-// (ade_update before the collision, J/c^2 added to the rest particle after
-// it) and the absorbing layer (the outgoing state scaled by 1 - sigma) -- as
-// the per-cell kernel applies them; no walls, no anisotropy.
-template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, bool EXT = false>
+// EXT: the cell extras as the per-cell kernel applies them, a bit mask (each
+// combination compiles only its own code: wall branches in the same kernel
+// as the general collision cost 45 % at 256^3).  Bit 1: walls -- a
+// population that would enter through a wall face is the cell's own outgoing
+// one in the opposite direction, with the reflection sign; the collision is
+// unchanged, so walls alone keep the closed-form store.  Bit 2: the
+// dispersion pole (ade_update before the collision, J/c^2 added to the rest
+// particle after it) and the absorbing layer (the outgoing state scaled by
+// 1 - sigma).  No anisotropy.
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, int EXT = 0>
 __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float* Mout, H* Dout,
                                            const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                            const RowGeo& g, const int b, const int* __restrict__ soff,
@@ -1694,13 +1701,21 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
         }
     };
 
-    // prologue: +z populations of plane z0-1, all of plane z0
+    // prologue: +z populations of plane z0-1, all of plane z0 (with a wall
+    // on z, plane 0 receives its own -z populations reflected instead)
     {
         const int zm = wrapz(z0 - 1);
+        const bool zwall0 = (EXT & 1) && bc.kind[2] != 0 && z0 == 0;
 #pragma unroll
         for (int k = 0; k < CX; ++k) {
             if (!ok[k]) continue;
             float o[3];
+            if (zwall0) {
+                row_pops_of<H, GH>(Min, Din, n, (int64_t)y * nx + xs[k], 6, o);
+#pragma unroll
+                for (int p = 0; p < P; ++p) pz_prev[k][p] = wall_negates<D>(bc, 3, p) ? -o[p] : o[p];
+                continue;
+            }
             row_pops_of<H, GH>(Min, Din, n, (int64_t)zm * nxy + (int64_t)y * nx + xs[k], 3, o);
 #pragma unroll
             for (int p = 0; p < P; ++p) pz_prev[k][p] = o[p];
@@ -1728,6 +1743,29 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
                 arr[k][3][p] = r < rows - 1 ? lp[(3 * 3 + p) * ROWC_MAX + rc + nx + x]     // -y from y+1
                                             : lh[(1 * 3 + p) * RX + x];
             }
+            if constexpr ((EXT & 1) != 0) {
+                // wall faces: the own outgoing population in the opposite direction
+                const bool wx = bc.kind[0] != 0, wy = bc.kind[1] != 0;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (wx && x == 0) {                                                   // +x: own -x
+                        const float v = lp[(2 * 3 + p) * ROWC_MAX + rc + x];
+                        arr[k][0][p] = wall_negates<D>(bc, 1, p) ? -v : v;
+                    }
+                    if (wx && x == nx - 1) {                                              // -x: own +x
+                        const float v = lp[(0 * 3 + p) * ROWC_MAX + rc + x];
+                        arr[k][2][p] = wall_negates<D>(bc, 4, p) ? -v : v;
+                    }
+                    if (wy && y == 0) {                                                   // +y: own -y
+                        const float v = lp[(3 * 3 + p) * ROWC_MAX + rc + x];
+                        arr[k][1][p] = wall_negates<D>(bc, 2, p) ? -v : v;
+                    }
+                    if (wy && y == ny - 1) {                                              // -y: own +y
+                        const float v = lp[(1 * 3 + p) * ROWC_MAX + rc + x];
+                        arr[k][3][p] = wall_negates<D>(bc, 5, p) ? -v : v;
+                    }
+                }
+            }
         }
         __syncthreads();
         // plane z+1: all of it while the march continues, else only its -z populations
@@ -1735,6 +1773,12 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
         if (z + 1 < z1) {
             decode_plane(zn, true, mz_new, pz_next, rest_next, cl2_next);
             decode_halo(zn);
+        } else if ((EXT & 1) && bc.kind[2] != 0 && z == nz - 1) {
+            // wall on z: the last plane receives its own +z populations reflected
+#pragma unroll
+            for (int k = 0; k < CX; ++k)
+#pragma unroll
+                for (int p = 0; p < P; ++p) mz_new[k][p] = wall_negates<D>(bc, 6, p) ? -pz_cur[k][p] : pz_cur[k][p];
         } else {
 #pragma unroll
             for (int k = 0; k < CX; ++k) {
@@ -1790,7 +1834,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
                 for (int a = 0; a < D; ++a) dl[a] = dlnmu[(int64_t)a * n + c];
                 add_mu_source<D, float>(K, cl2, dl, Sp);
             }
-            if constexpr (!EXT) {
+            if constexpr ((EXT & 2) == 0) {
                 dev_collide_store<D, H, GH, NTS>(f, cl2, wc0, Sp, any_src, omega, tau_half != 0, rho, K, n,
                                                  (int)c, Mout, Dout);
             } else {
@@ -1828,7 +1872,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
     }
 }
 
-template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, bool EXT = false>
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, int EXT = 0>
 __global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
                                                    const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                    const RowGeo g, const int* __restrict__ soff,

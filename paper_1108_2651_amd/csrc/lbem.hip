@@ -534,18 +534,18 @@ struct DevImpl : Impl {
         const int P = Lat<D>::P;
         return (H*)(h->pop[k] + align256((size_t)(P + D) * h->n * 4));
     }
-    template <bool MU, bool NTS, int NTB, bool EXT = false>
+    template <bool MU, bool NTS, int NTB, int EXT = 0>
     static void go_row_n(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
     {
         hipLaunchKernelGGL((k_step_dev3r<H, GH, MU, NTS, 2, NTB, EXT>), dim3(h->rgeo.nblocks), dim3(NTB), 0,
                            h->stream, M(h, from), Dv(h, from), M(h, to), Dv(h, to), (const float*)h->cl2,
                            (const float*)h->dlnmu, h->rgeo, so, h->rsrc_ent, h->rsrc_val, amp, om, th, ext_of(h));
     }
-    // the row-tile step with the extras that leave the streaming alone
-    // (dispersion, absorbing layer): 512-thread tiles, no walls, no anisotropy
+    // the row-tile step with cell extras (walls, dispersion, absorbing
+    // layer): 512-thread tiles, no anisotropy
     static bool row_ext_ok(const lbem_s* h)
     {
-        return h->rowk && !ext_of(h).walls() && !h->ra_set && h->rgeo.tpr * h->rgeo.ty == 512;
+        return h->rowk && !h->ra_set && h->rgeo.tpr * h->rgeo.ty == 512;
     }
     template <bool MU>
     static hipError_t go_row(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
@@ -566,17 +566,27 @@ struct DevImpl : Impl {
             return hipErrorInvalidValue;
         }
     }
-    template <int RM, int V, bool MU, bool BX = false>
+    // BX: 0 no cell extras, 1 walls only, 2 walls, dispersion and absorber
+    template <int RM, int V, bool MU, int BX = 0>
     static hipError_t go(lbem_s* h, int from, int to, float amp)
     {
         SrcArgs<float> s;
-        if constexpr (D == 3 && BX && RM == R_PULL) {
+        if constexpr (D == 3 && BX != 0 && RM == R_PULL) {
             if (row_ext_ok(h)) {
                 const int* so = h->nrsrc ? h->rsrc_off : nullptr;
                 const float om = (float)(1.0 / h->cfg.tau);
                 const int th = h->cfg.tau == 0.5;
-                if (h->nts) go_row_n<MU, true, 512, true>(h, from, to, so, amp, om, th);
-                else go_row_n<MU, false, 512, true>(h, from, to, so, amp, om, th);
+                // row extras mask: 1 walls, 2 dispersion / absorber
+                if constexpr (BX == 1) {
+                    if (h->nts) go_row_n<MU, true, 512, 1>(h, from, to, so, amp, om, th);
+                    else go_row_n<MU, false, 512, 1>(h, from, to, so, amp, om, th);
+                } else if (ext_of(h).walls()) {
+                    if (h->nts) go_row_n<MU, true, 512, 3>(h, from, to, so, amp, om, th);
+                    else go_row_n<MU, false, 512, 3>(h, from, to, so, amp, om, th);
+                } else {
+                    if (h->nts) go_row_n<MU, true, 512, 2>(h, from, to, so, amp, om, th);
+                    else go_row_n<MU, false, 512, 2>(h, from, to, so, amp, om, th);
+                }
                 return hipGetLastError();
             }
         }
@@ -628,8 +638,11 @@ struct DevImpl : Impl {
     static hipError_t go_v(lbem_s* h, int from, int to, float amp)
     {
         if (has_bx(h)) {
-            if (h->mu_set) return go<RM, 1, true, true>(h, from, to, amp);
-            return go<RM, 1, false, true>(h, from, to, amp);
+            // walls only: the closed-form collision (no anisotropy in 16 bits)
+            const bool walls_only = h->ade == nullptr && h->keep == nullptr;
+            if (h->mu_set)
+                return walls_only ? go<RM, 1, true, 1>(h, from, to, amp) : go<RM, 1, true, 2>(h, from, to, amp);
+            return walls_only ? go<RM, 1, false, 1>(h, from, to, amp) : go<RM, 1, false, 2>(h, from, to, amp);
         }
         if (h->mu_set) return go<RM, 1, true>(h, from, to, amp);
         switch (h->vec) {

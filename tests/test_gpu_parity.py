@@ -432,19 +432,22 @@ def test_deviation_row_kernel_bitwise(shape, mu):
 @pytest.mark.parametrize("shape,mu", [((64, 40, 20), True), ((100, 9, 7), False), ((33, 17, 37), False),
                                       ((128, 6, 1), True), ((300, 4, 6), False)])
 def test_row_kernel_with_extras_bitwise(shape, mu):
-    """The row-tile step with the extras that leave the streaming alone -- the
-    dispersion pole (auxiliary fields updated in place) and the absorbing
-    layer -- leaves the same state, bit for bit, as the per-cell kernel with
-    the same extras: every 16-bit format, each extra alone and both, sources,
-    mu, ragged rows and tiles, one-plane boxes."""
+    """The row-tile step with cell extras -- PEC/PMC walls on one, two or three
+    axes (reflection from the cell's own outgoing state at the x, y and z
+    faces), the dispersion pole (auxiliary fields updated in place) and the
+    absorbing layer -- leaves the same state, bit for bit, as the per-cell
+    kernel with the same extras: every 16-bit format, each extra alone and
+    together, sources, mu, ragged rows and tiles, one-plane boxes."""
     from paper_1108_2651_amd import lbem
     steps = 19
     p = random_problem(3, shape, seed=sum(shape) + 71, mu=mu, nsteps=steps)
     rng = np.random.default_rng(sum(shape) + 72)
     wp2, w02, gam = rng.uniform(0, 0.02, p.n), rng.uniform(0, 0.03, p.n), rng.uniform(0, 0.01, p.n)
     sigma = np.where(rng.random(p.n) < 0.3, rng.uniform(0, 0.05, p.n), 0.0)
+    wall_sets = {"walls-x-pec": [(0, "pec")], "walls-yz": [(1, "pmc"), (2, "pec")],
+                 "walls-all": [(0, "pmc"), (1, "pec"), (2, "pmc")]}
     for prec in LOWP:
-        for extras in ("dispersion", "absorber", "both"):
+        for extras in ("dispersion", "absorber", "both", "walls-x-pec", "walls-yz", "walls-all+both"):
             states = []
             for row in ("0", "1"):
                 os.environ.update(LBEM_DEV3Z="1", LBEM_DEV3R=row)
@@ -453,10 +456,12 @@ def test_row_kernel_with_extras_bitwise(shape, mu):
                 finally:
                     os.environ.pop("LBEM_DEV3Z", None)
                     os.environ.pop("LBEM_DEV3R", None)
+                for a, kind in wall_sets.get(extras.split("+")[0], []):
+                    s.set_boundary(a, kind)
                 s.set_medium(p.eps_r, p.mu_r)
-                if extras != "dispersion":
+                if extras in ("absorber", "both", "walls-all+both"):
                     s.set_absorber(sigma)
-                if extras != "absorber":
+                if extras in ("dispersion", "both", "walls-all+both"):
                     s.set_dispersion(wp2, w02, gam)
                 s.init_fields(p.E0, p.B0)
                 s.set_source(p.src_comp, p.src_cells, p.src_weights)
