@@ -1596,7 +1596,10 @@ __device__ __forceinline__ void row_pops_of(const float* Min, const H* Din, int6
 // At least four waves per SIMD (<= 128 VGPRs): two 512-thread blocks per CU.
 // With fewer, one block holds a CU and the latency of its loads between the
 // barriers of a plane has nothing to hide it (measured 3.19 -> 4.38 ms at
-// 512^3 when a change took the kernel to 141 VGPRs).
+// 512^3 when a change took the kernel to 141 VGPRs).  The Dev-Q
+// instantiations with cell extras ask for three: at the four-wave target the
+// scheduler issued their 21 code loads one at a time (load, wait, convert);
+// at three it keeps them in flight and still allocates <= 128 VGPRs.
 // One tile (block b of the tiling g) of the row-tile step; every thread of the
 // block calls it (it holds barriers).  lp: 12 * CX * NTB floats, lh: 6 * RX
 // floats of LDS.
@@ -1873,7 +1876,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
 }
 
 template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, int EXT = 0>
-__global__ __launch_bounds__(NTB, 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
+__global__ __launch_bounds__(NTB, (EXT != 0 && !GH) ? 3 : 4) void k_step_dev3r(const float* Min, const H* Din, float* Mout, H* Dout,
                                                    const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                                    const RowGeo g, const int* __restrict__ soff,
                                                    const int2* __restrict__ sent, const float* __restrict__ sval,
