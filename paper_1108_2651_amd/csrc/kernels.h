@@ -1619,7 +1619,7 @@ struct RowLds {
 // dispersion pole (ade_update before the collision, J/c^2 added to the rest
 // particle after it) and the absorbing layer (the outgoing state scaled by
 // 1 - sigma).  No anisotropy.
-template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, int EXT = 0>
+template <typename H, bool GH, bool MU, bool NTS, int CX, int NTB, int EXT = 0, bool HALO2 = false>
 __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float* Mout, H* Dout,
                                            const float* __restrict__ cl2a, const float* __restrict__ dlnmu,
                                            const RowGeo& g, const int b, const int* __restrict__ soff,
@@ -1692,15 +1692,38 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
             }
         }
     };
-    // the +y populations of row y0-1 and the -y ones of row y0+rows, plane zz
+    // the +y populations of row y0-1 and the -y ones of row y0+rows, plane zz.
+    // HALO2: one pass per row, its velocity fixed at compile time; otherwise
+    // one pass over both rows with the velocity chosen per item.  Which one
+    // the compiler schedules better depends on the instantiation: for the
+    // single-lattice ghost kernel the run-time velocity made the decode pick
+    // its codes in branches and load them one at a time, while the two passes
+    // make the Dev-Q and batched kernels issue their code loads one at a time.
     auto decode_halo = [&](int zz) {
-        for (int t = threadIdx.x; t < 2 * nx; t += NTB) {
-            const int side = t >= nx, x = t - side * nx;
-            const int64_t c = (int64_t)zz * nxy + (int64_t)(side ? yh1 : yh0) * nx + x;
-            float o[3];
-            row_pops_of<H, GH>(Min, Din, n, c, side ? 5 : 2, o);
+        if constexpr (HALO2) {
+            const int64_t r0 = (int64_t)zz * nxy + (int64_t)yh0 * nx;
+            const int64_t r1 = (int64_t)zz * nxy + (int64_t)yh1 * nx;
+            for (int x = threadIdx.x; x < nx; x += NTB) {
+                float o[3];
+                row_pops_of<H, GH>(Min, Din, n, r0 + x, 2, o);
 #pragma unroll
-            for (int p = 0; p < P; ++p) lh[(side * 3 + p) * RX + x] = o[p];
+                for (int p = 0; p < P; ++p) lh[(0 * 3 + p) * RX + x] = o[p];
+            }
+            for (int x = threadIdx.x; x < nx; x += NTB) {
+                float o[3];
+                row_pops_of<H, GH>(Min, Din, n, r1 + x, 5, o);
+#pragma unroll
+                for (int p = 0; p < P; ++p) lh[(1 * 3 + p) * RX + x] = o[p];
+            }
+        } else {
+            for (int t = threadIdx.x; t < 2 * nx; t += NTB) {
+                const int side = t >= nx, x = t - side * nx;
+                const int64_t c = (int64_t)zz * nxy + (int64_t)(side ? yh1 : yh0) * nx + x;
+                float o[3];
+                row_pops_of<H, GH>(Min, Din, n, c, side ? 5 : 2, o);
+#pragma unroll
+                for (int p = 0; p < P; ++p) lh[(side * 3 + p) * RX + x] = o[p];
+            }
         }
     };
 
@@ -1884,7 +1907,7 @@ __global__ __launch_bounds__(NTB, (EXT != 0 && !GH) ? 3 : 4) void k_step_dev3r(c
                                                    const CellExt bc)
 {
     __shared__ float lds[RowLds<CX, NTB>::FLOATS];
-    dev3r_tile<H, GH, MU, NTS, CX, NTB, EXT>(Min, Din, Mout, Dout, cl2a, dlnmu, g,
+    dev3r_tile<H, GH, MU, NTS, CX, NTB, EXT, GH && EXT == 0>(Min, Din, Mout, Dout, cl2a, dlnmu, g,
                                              remap_block(blockIdx.x, g.nblocks, g.xcd), soff, sent, sval, amp,
                                              omega, tau_half, lds, lds + 12 * RowLds<CX, NTB>::ROWC_MAX, bc);
 }
