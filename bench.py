@@ -215,7 +215,7 @@ def run_workload(name: str, prec: str, steps: int, warmup: int, streaming: str =
 
 # the headline: config 4 with FP16 deviation storage in ghost coordinates
 PRIMARY_PREC = "f16ghost"
-PRIMARY_KERNEL = "k_step_dev3r<__half,ghost,mu=0,nts=1,cx=2,512>"
+PRIMARY_KERNEL = "k_step_dev3r<__half,ghost,mu=0,nts=1,cx=2,512,ext=0>"
 PRIMARY_TRAFFIC = "c4_512_f16ghost"
 CPU_SAMPLE_CROP = 128
 
