@@ -64,10 +64,15 @@ bool valid_cfg(const lbem_config* c)
     return true;
 }
 
-// Boxes below this many cells (about 180^3) are served from the Infinity
-// Cache; there the 3D multi-step kernels cannot fill the chip and single steps
-// are faster (measured from 64^3 to 256^3).
-constexpr double SMALL3D = 6.0e6;
+// Below this many cells (about 152^3) a 3D state is served from the Infinity
+// Cache, where the 3D z-marching kernels cannot fill the chip and single
+// per-cell steps are as fast or faster.  Measured per update: FP32 fused pair
+// against single AA steps 144^3 35.1k / 36.1k MLUPS, 160^3 38.6k / 31.0k,
+// 176^3 37.6k / 24.5k; FP16 ghost row tiles against per-cell tiles 128^3
+// 36.6k / 43.3k, 144^3 30.9k / 24.5k, 160^3 33.2k / 26.9k.
+constexpr double SMALL3D = 3.5e6;
+// plain FP16 storage on whole-row blocks: measured from 6e6 cells on
+constexpr double XROW3D = 6.0e6;
 
 int resolve_streaming(const lbem_config* c)
 {
@@ -844,7 +849,7 @@ static void make_xrow_geo(lbem_s* h)
 {
     const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
     const bool plain = h->prec <= LBEM_F32 || h->prec == LBEM_F16;
-    const int dflt = h->prec == LBEM_F16 && (double)h->n >= SMALL3D;
+    const int dflt = h->prec == LBEM_F16 && (double)h->n >= XROW3D;
     h->xrow = (h->D == 3 && plain && nx <= 2 * NT && h->vec == 1) ? env_int("LBEM_XROW", dflt) : 0;
     if (!h->xrow) return;     // rows longer than 2*NT have no whole-row tiling (no rows per block)
     XRowGeo& g = h->xgeo;
