@@ -1524,8 +1524,10 @@ __global__ __launch_bounds__(NT) void k_step_dev3z(const float* Min, const H* Di
 // 3D deviation storage, row tiles: every stored cell decoded once
 // ---------------------------------------------------------------------------
 // A block of NTB threads owns `ty` whole x-rows (y0 .. y0+rows-1) of a chunk
-// of `lz` planes and marches along z.  A thread owns up to CX cells of one row
-// (x = q + k*tpr).  Per plane it reads its cells' stored moments and 16-bit
+// of `lz` planes and marches along z.  The tile's rows are contiguous in a
+// plane; a thread owns up to CX of its cells, the ones at tile-flat indices
+// threadIdx.x + k*NTB, so that every wave loads consecutive cells whatever
+// the row length.  Per plane it reads its cells' stored moments and 16-bit
 // codes once, with aligned loads, and decodes every outgoing population (rest
 // and dropped ghost entries included) in FP32; the +-x and +-y ones go to LDS
 // for the in-plane neighbours, the +-z and rest ones stay in registers for
@@ -1538,7 +1540,7 @@ constexpr int ROWX_MAX = 1024;   // longest row
 
 struct RowGeo {
     int nx, ny, nz;
-    int tpr, ty;          // threads per row (multiple of 64, CX*tpr >= nx), rows per tile (NTB / tpr)
+    int ty;               // rows per tile (CX * NTB / nx)
     int tiles_y, lz, nblocks, xcd;
     int64_t n;
 };
@@ -1639,18 +1641,20 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
     const int rows = min(g.ty, g.ny - y0);
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int64_t n = g.n, nxy = (int64_t)nx * ny;
-    const int r = threadIdx.x / g.tpr, q = threadIdx.x % g.tpr;
-    const bool row_ok = r < rows;
-    const int y = y0 + r;
+    const int64_t ty0 = (int64_t)y0 * nx;          // first cell of the tile within a plane
     const int yh0 = (y0 - 1 + ny) % ny, yh1 = (y0 + rows) % ny;
     const bool has_src = soff != nullptr;
 
-    int xs[CX];
+    // cell k of the thread: tile-flat index fl (also its LDS slot and its
+    // source key), row rr, column xs
+    int fl[CX], rr[CX], xs[CX];
     bool ok[CX];
 #pragma unroll
     for (int k = 0; k < CX; ++k) {
-        xs[k] = q + k * g.tpr;
-        ok[k] = row_ok && xs[k] < nx;
+        fl[k] = (int)threadIdx.x + k * NTB;
+        rr[k] = fl[k] / nx;
+        xs[k] = fl[k] - rr[k] * nx;
+        ok[k] = rr[k] < rows;
     }
     auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
 
@@ -1661,11 +1665,11 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
     // to_lds), -z to mz, +z to pz, rest to rs
     auto decode_plane = [&](int zz, bool to_lds, float (&mz)[CX][P], float (&pz)[CX][P], float (&rs)[CX][P],
                             float (&cl)[CX]) {
-        const int64_t zo = (int64_t)zz * nxy + (int64_t)y * nx;
+        const int64_t zo = (int64_t)zz * nxy + ty0;
 #pragma unroll
         for (int k = 0; k < CX; ++k) {
             if (!ok[k]) continue;
-            const int64_t c = zo + xs[k];
+            const int64_t c = zo + fl[k];
             float Mv[NM], cd[NC];
 #pragma unroll
             for (int t = 0; t < NM; ++t) Mv[t] = Min[(int64_t)t * n + c];
@@ -1687,7 +1691,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
                     for (int p = 0; p < P; ++p)
-                        lp[(j * 3 + p) * ROWC_MAX + r * nx + xs[k]] =
+                        lp[(j * 3 + p) * ROWC_MAX + fl[k]] =
                             row_pop<GH>(Mv, get, sc, wc0, inplane_vel(j), p);
             }
         }
@@ -1737,12 +1741,12 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
             if (!ok[k]) continue;
             float o[3];
             if (zwall0) {
-                row_pops_of<H, GH>(Min, Din, n, (int64_t)y * nx + xs[k], 6, o);
+                row_pops_of<H, GH>(Min, Din, n, ty0 + fl[k], 6, o);
 #pragma unroll
                 for (int p = 0; p < P; ++p) pz_prev[k][p] = wall_negates<D>(bc, 3, p) ? -o[p] : o[p];
                 continue;
             }
-            row_pops_of<H, GH>(Min, Din, n, (int64_t)zm * nxy + (int64_t)y * nx + xs[k], 3, o);
+            row_pops_of<H, GH>(Min, Din, n, (int64_t)zm * nxy + ty0 + fl[k], 3, o);
 #pragma unroll
             for (int p = 0; p < P; ++p) pz_prev[k][p] = o[p];
         }
@@ -1757,37 +1761,38 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
 #pragma unroll
         for (int k = 0; k < CX; ++k) {
             if (!ok[k]) continue;
-            const int x = xs[k];
+            const int x = xs[k], i = fl[k];
             const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-            const int rc = r * nx;
+            const int rc = i - x;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 arr[k][0][p] = lp[(0 * 3 + p) * ROWC_MAX + rc + xm];                       // +x from x-1
                 arr[k][2][p] = lp[(2 * 3 + p) * ROWC_MAX + rc + xp];                       // -x from x+1
-                arr[k][1][p] = r > 0 ? lp[(1 * 3 + p) * ROWC_MAX + rc - nx + x]            // +y from y-1
-                                     : lh[(0 * 3 + p) * RX + x];
-                arr[k][3][p] = r < rows - 1 ? lp[(3 * 3 + p) * ROWC_MAX + rc + nx + x]     // -y from y+1
-                                            : lh[(1 * 3 + p) * RX + x];
+                arr[k][1][p] = rr[k] > 0 ? lp[(1 * 3 + p) * ROWC_MAX + i - nx]             // +y from y-1
+                                         : lh[(0 * 3 + p) * RX + x];
+                arr[k][3][p] = rr[k] < rows - 1 ? lp[(3 * 3 + p) * ROWC_MAX + i + nx]      // -y from y+1
+                                                : lh[(1 * 3 + p) * RX + x];
             }
             if constexpr ((EXT & 1) != 0) {
                 // wall faces: the own outgoing population in the opposite direction
                 const bool wx = bc.kind[0] != 0, wy = bc.kind[1] != 0;
+                const int y = y0 + rr[k];
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     if (wx && x == 0) {                                                   // +x: own -x
-                        const float v = lp[(2 * 3 + p) * ROWC_MAX + rc + x];
+                        const float v = lp[(2 * 3 + p) * ROWC_MAX + i];
                         arr[k][0][p] = wall_negates<D>(bc, 1, p) ? -v : v;
                     }
                     if (wx && x == nx - 1) {                                              // -x: own +x
-                        const float v = lp[(0 * 3 + p) * ROWC_MAX + rc + x];
+                        const float v = lp[(0 * 3 + p) * ROWC_MAX + i];
                         arr[k][2][p] = wall_negates<D>(bc, 4, p) ? -v : v;
                     }
                     if (wy && y == 0) {                                                   // +y: own -y
-                        const float v = lp[(3 * 3 + p) * ROWC_MAX + rc + x];
+                        const float v = lp[(3 * 3 + p) * ROWC_MAX + i];
                         arr[k][1][p] = wall_negates<D>(bc, 2, p) ? -v : v;
                     }
                     if (wy && y == ny - 1) {                                              // -y: own +y
-                        const float v = lp[(1 * 3 + p) * ROWC_MAX + rc + x];
+                        const float v = lp[(1 * 3 + p) * ROWC_MAX + i];
                         arr[k][3][p] = wall_negates<D>(bc, 5, p) ? -v : v;
                     }
                 }
@@ -1810,7 +1815,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
             for (int k = 0; k < CX; ++k) {
                 if (!ok[k]) continue;
                 float o[3];
-                row_pops_of<H, GH>(Min, Din, n, (int64_t)zn * nxy + (int64_t)y * nx + xs[k], 6, o);
+                row_pops_of<H, GH>(Min, Din, n, (int64_t)zn * nxy + ty0 + fl[k], 6, o);
 #pragma unroll
                 for (int p = 0; p < P; ++p) mz_new[k][p] = o[p];
             }
@@ -1825,8 +1830,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
 #pragma unroll
         for (int k = 0; k < CX; ++k) {
             if (!ok[k]) continue;
-            const int x = xs[k];
-            const int64_t c = (int64_t)z * nxy + (int64_t)y * nx + x;
+            const int64_t c = (int64_t)z * nxy + ty0 + fl[k];
             float f[Q][P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -1844,7 +1848,7 @@ __device__ __forceinline__ void dev3r_tile(const float* Min, const H* Din, float
             moments<D, float>(f, rho, K);
 #pragma unroll
             for (int p = 0; p < P; ++p) Sp[p] = 0.f;
-            const int loc = r * nx + x;
+            const int loc = fl[k];
             for (int e = s0; e < s1; ++e) {
                 const int2 en = sent[e];
                 if (en.x == loc) {
@@ -2408,20 +2412,21 @@ __global__ __launch_bounds__(NT) void k_step_batch_dev(const BatchHdr* __restric
     }
 }
 
-// 3D deviation members on the whole-row tiling (rows of up to 2 NT cells):
-// the row-tile step, work items numbered by row_base (the member's RowGeo
-// blocks).  A tick launches it for steps after its first when every member of
+// 3D deviation members on the whole-row tiling (rows of up to 2 BROW_NT
+// cells): the row-tile step, work items numbered by row_base (the member's
+// RowGeo blocks), BROW_NT threads per block.  A tick launches it for steps after its first when every member of
 // the class is on that tiling and all or none of them have a varying mu (MU);
 // otherwise, and for the first step (which may start from the natural layout),
 // the per-cell kernel above.  This kernel holds nothing but the row tile: with
 // the per-cell paths or a run-time mu branch in the same kernel the compiler
 // issues the code loads of a plane one at a time (measured 1.8x slower).
+constexpr int BROW_NT = 512;
 template <typename H, bool GH, bool MU>
-__global__ __launch_bounds__(NT, 4) void k_step_batch_dev3_rows(const BatchHdr* __restrict__ hdr,
-                                                             const BatchGrid* __restrict__ tab, int k)
+__global__ __launch_bounds__(BROW_NT, 4) void k_step_batch_dev3_rows(const BatchHdr* __restrict__ hdr,
+                                                                  const BatchGrid* __restrict__ tab, int k)
 {
     constexpr int CX = 2;
-    using L = RowLds<CX, NT>;
+    using L = RowLds<CX, BROW_NT>;
     __shared__ float lds[L::FLOATS];
     const int count = hdr->count, total = hdr->total_rows;
     for (int w = blockIdx.x; w < total; w += gridDim.x) {
@@ -2430,7 +2435,7 @@ __global__ __launch_bounds__(NT, 4) void k_step_batch_dev3_rows(const BatchHdr* 
         if (k >= G.nsteps) continue;
         const int s = (G.cur0 + k) & 1;
         const RowGeo rg = G.rgeo;       // held in registers: the tile's stores cannot alias it
-        dev3r_tile<H, GH, MU, false, CX, NT>(
+        dev3r_tile<H, GH, MU, false, CX, BROW_NT>(
             gmem<const float>(G.buf[s]), gmem<const H>(G.dev[s]), gmem<float>(G.buf[s ^ 1]), gmem<H>(G.dev[s ^ 1]),
             gmem<const float>(G.cl2), MU ? gmem<const float>(G.dlnmu) : nullptr, rg, w - G.row_base,
             G.rsrc_off ? gmem<const int>(G.rsrc_off) : nullptr, gmem<const int2>(G.rsrc_ent),

@@ -71,6 +71,13 @@ bool valid_cfg(const lbem_config* c)
 // 176^3 37.6k / 24.5k; FP16 ghost row tiles against per-cell tiles 128^3
 // 36.6k / 43.3k, 144^3 30.9k / 24.5k, 160^3 33.2k / 26.9k.
 constexpr double SMALL3D = 3.5e6;
+// The 3D 16-bit formats take the whole-row tiles once the state one step
+// touches (stored values read and written, c_L^2 read: 112 B per cell with
+// ghost coordinates, 136 B with all deviations) exceeds the 256 MB Infinity
+// Cache; per-cell tiles below.  Measured, us per step, per-cell against row
+// tiles: FP16 ghost 128^3 (224 MiB) 48.4 / 67.1, 144^3 122.1 / 88.2; FP16-dev
+// 128^3 (272 MiB) 76.3 / 74.5, 144^3 130.7 / 109.3.
+constexpr double ROWTILE_BYTES = 256.0 * (1 << 20);
 // plain FP16 storage on whole-row blocks: measured from 6e6 cells on
 constexpr double XROW3D = 6.0e6;
 
@@ -167,12 +174,13 @@ struct lbem_s {
     // 3D deviation kernel on whole-row tiles (k_step_dev3r), marching along z
     int rowk;
     RowGeo rgeo;
+    int rntb;            // threads per block of the row tiles
     int* rsrc_off;
     int2* rsrc_ent;
     float* rsrc_val;
     int64_t nrsrc;
     // the whole-row tiling of this handle inside a batch (3D deviation formats,
-    // rows of up to 2 NT cells; 256-thread blocks) and its source table
+    // rows of up to 2 BROW_NT cells, BROW_NT-thread blocks) and its source table
     int brow;
     RowGeo bgeo;
     int* bsrc_off;
@@ -550,13 +558,13 @@ struct DevImpl : Impl {
     // layer): 512-thread tiles, no anisotropy
     static bool row_ext_ok(const lbem_s* h)
     {
-        return h->rowk && !h->ra_set && h->rgeo.tpr * h->rgeo.ty == 512;
+        return h->rowk && !h->ra_set && h->rntb == 512;
     }
     template <bool MU>
     static hipError_t go_row(lbem_s* h, int from, int to, const int* so, float amp, float om, int th)
     {
         if constexpr (D == 3) {
-            const int nb = h->rgeo.tpr * h->rgeo.ty;
+            const int nb = h->rntb;
             if (h->nts) {
                 if (nb == 1024) go_row_n<MU, true, 1024>(h, from, to, so, amp, om, th);
                 else if (nb == 512) go_row_n<MU, true, 512>(h, from, to, so, amp, om, th);
@@ -825,7 +833,12 @@ static void make_fused_geo(lbem_s* h)
 
 static void make_zmarch_geo(lbem_s* h)
 {
-    h->zmarch = (h->D == 3 && is_dev(h->prec)) ? env_int("LBEM_DEV3Z", (double)h->n >= SMALL3D) : 0;
+    // rows the row tiles take (with the default 512-thread block) go by the
+    // state size, longer ones by the cell count
+    const bool ghost = h->prec == LBEM_F16GHOST || h->prec == LBEM_BF16GHOST;
+    const bool big = h->cfg.nx <= ROWX_MAX ? (double)h->n * (ghost ? 112.0 : 136.0) > ROWTILE_BYTES
+                                           : (double)h->n >= SMALL3D;
+    h->zmarch = (h->D == 3 && is_dev(h->prec)) ? env_int("LBEM_DEV3Z", big) : 0;
     h->zlz = std::max(1, env_int("LBEM_DEV3Z_LZ", 16));
     Geo& g = h->zgeo;
     g = h->geo;
@@ -862,10 +875,11 @@ static void make_xrow_geo(lbem_s* h)
     g.nblocks = g.tiles_y * nz;
 }
 
-// Whole-row tiles of k_step_dev3r: CX = 2 cells per thread, tpr threads per
-// row (a power of two from 64 up to the block size), ty = block/tpr rows per
-// tile; z chunks as long as still give >= 1024 blocks.  Rows longer than
-// twice the block (or ROWX_MAX) keep the column-tile z-march.
+// Whole-row tiles of k_step_dev3r: CX = 2 cells per thread numbered through
+// the tile's rows (short rows leave no thread idle and keep every wave on
+// consecutive cells), 2 block / nx rows per tile; the planes per chunk are
+// chosen below.  Rows longer than twice the block (or ROWX_MAX) keep the
+// column-tile z-march.
 static void make_row_geo(lbem_s* h)
 {
     const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
@@ -877,41 +891,61 @@ static void make_row_geo(lbem_s* h)
     h->rowk = (h->zmarch && nx <= std::min(ROWX_MAX, 2 * ntb)) ? env_int("LBEM_DEV3R", 1) : 0;
     RowGeo& g = h->rgeo;
     g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
-    int tpr = 64;
-    while (2 * tpr < nx) tpr <<= 1;
-    if (tpr > ntb) tpr = ntb;
-    g.tpr = tpr;
-    g.ty = ntb / tpr;
-    g.tiles_y = (ny + g.ty - 1) / g.ty;
+    h->rntb = ntb;
     // Measured (512^3 and 256^3, FP16 ghost and Dev-Q): blocks dealt to the
     // XCDs in turn, so that the blocks resident at a time are neighbouring
     // tiles of one z band, run 5-7 % faster than contiguous tile ranges per XCD
     // (512^3 ghost 2.95 against 3.20 ms); runs of 8 neighbouring tiles per XCD
     // (their y-halo rows shared in one L2) another 0.8-1.2 % (2.92 ms; runs
-    // of 2, 4 or 16 within 0.5 % of it).  Chunks of 7 planes: 512^3 ghost
-    // 2.909-2.913 ms against 2.917-2.925 with 8 (16: 2.945), 256^3 ghost
-    // 0.366 against 0.379 ms, Dev-Q 0.438 against 0.448 (5 planes is 1 %
-    // faster at 256^3 and 0.7 % slower at 512^3).
-    int lz = 7;
-    while (lz > 1 && (int64_t)g.tiles_y * ((nz + lz - 1) / lz) < 1024) lz /= 2;
+    // of 2, 4 or 16 within 0.5 % of it).
+    // As many rows per tile as the block holds: rows of a power-of-two thread
+    // count with idle threads ran slower (FP16 ghost, us per step: 160^3 123
+    // against 106, 320^3 796 against 732, 384^3 1326 against 1276), and so did
+    // fewer rows with more blocks (192^3: 4 rows 171-183 against 5 rows 166).
+    // Planes per chunk: the longest of 1..7 whose last round of resident
+    // blocks (1024 / block threads per CU) is within 0.08 of the fullest,
+    // among the lengths that give at least two rounds of blocks (all of them if
+    // none does).  A thin last round costs more than the chunk ends decoded
+    // twice: FP16 ghost, planes -> us per step, 192^3 (5 rows) 3 166, 5 166,
+    // 6 176, 7 190; 160^3 (6 rows) 3 106, 4 120, 5 109; 144^3 (7 rows) 2 88,
+    // 3 107; 512^3 (2 rows) 7 2909-2913, 8 2917-2925, 16 2945.
+    int cus = 256, dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+        cus = v;
+    const int64_t slots = (int64_t)cus * (1024 / ntb);
+    const int tymax = std::max(1, 2 * ntb / nx);
+    g.ty = std::max(1, std::min(tymax, env_int("LBEM_DEV3R_TY", tymax)));
+    g.tiles_y = (ny + g.ty - 1) / g.ty;
+    auto nblk = [&](int c) { return (int64_t)g.tiles_y * ((nz + c - 1) / c); };
+    auto fill = [&](int c) {
+        const int64_t nb = nblk(c);
+        return (double)nb / (double)(((nb + slots - 1) / slots) * slots);
+    };
+    const bool two = nblk(1) >= 2 * slots;
+    double best = 0.0;
+    for (int c = 1; c <= 7; ++c)
+        if (!two || nblk(c) >= 2 * slots) best = std::max(best, fill(c));
+    int lz = 1;
+    for (int c = 7; c >= 1; --c)
+        if ((!two || nblk(c) >= 2 * slots) && fill(c) >= best - 0.08) { lz = c; break; }
     g.lz = std::max(1, env_int("LBEM_DEV3R_LZ", lz));
     g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
     g.xcd = env_int("LBEM_DEV3R_XCD", 8);
 }
 
-// The whole-row tiling of a 3D deviation handle inside a batch: 256-thread
-// blocks (the batched kernel's), two cells per thread and ceil(nx/2) threads
-// per row, so short rows fill the block (nx = 32: 16 rows per tile); chunks of
-// 8 planes.  Rows longer than 2 NT cells keep the per-cell tiles.
+// The whole-row tiling of a 3D deviation handle inside a batch: blocks of
+// BROW_NT threads, two cells per thread numbered through the tile's rows,
+// 2 BROW_NT / nx rows per tile (nx = 64: 16 rows); chunks of 8 planes.
+// Rows longer than 2 BROW_NT cells keep the per-cell tiles.
 static void make_batch_row_geo(lbem_s* h)
 {
     const int nx = (int)h->cfg.nx, ny = (int)h->cfg.ny, nz = (int)h->cfg.nz;
-    h->brow = (h->D == 3 && is_dev(h->prec) && nx <= 2 * NT) ? env_int("LBEM_BATCH_ROW", 1) : 0;
+    h->brow = (h->D == 3 && is_dev(h->prec) && nx <= std::min(ROWX_MAX, 2 * BROW_NT)) ? env_int("LBEM_BATCH_ROW", 1) : 0;
     if (!h->brow) return;
     RowGeo& g = h->bgeo;
     g.nx = nx; g.ny = ny; g.nz = nz; g.n = h->n;
-    g.tpr = (nx + 1) / 2;
-    g.ty = NT / g.tpr;
+    g.ty = 2 * BROW_NT / nx;
     g.tiles_y = (ny + g.ty - 1) / g.ty;
     g.lz = std::max(1, env_int("LBEM_BATCH_ROW_LZ", 8));
     g.nblocks = g.tiles_y * ((nz + g.lz - 1) / g.lz);
@@ -1933,11 +1967,11 @@ static void launch_batch_dev(dim3 g, dim3 t, hipStream_t st, const BatchHdr* hdr
 {
     if constexpr (D == 3) {
         if (k > 0 && mode == MODE_ROWS) {
-            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, false>), g, t, 0, st, hdr, tab, k);
+            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, false>), g, dim3(BROW_NT), 0, st, hdr, tab, k);
             return;
         }
         if (k > 0 && mode == MODE_ROWS_MU) {
-            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, true>), g, t, 0, st, hdr, tab, k);
+            hipLaunchKernelGGL((k_step_batch_dev3_rows<H, GH, true>), g, dim3(BROW_NT), 0, st, hdr, tab, k);
             return;
         }
     }
@@ -2184,7 +2218,7 @@ int lbem_batch_create(int max_lattices, int steps_per_tick, void* stream, lbem_b
     // classes hold a few small lattices, 37.2 against 38.6 GLUPS with the row
     // tiles always on (100 req/s: p50 141 against 62 ms).  So a class takes
     // them only with enough items to fill the GPU several times over.
-    b->rows_min = std::max(0, env_int("LBEM_BATCH_ROWS_MIN", 3072));
+    b->rows_min = std::max(0, env_int("LBEM_BATCH_ROWS_MIN", 1536));
     b->amp_off = class_bytes(max_lattices) * NCLASS;
     const size_t bytes = b->amp_off + align256((size_t)max_lattices * steps_per_tick * 8);
     b->dev = nullptr;

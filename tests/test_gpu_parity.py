@@ -411,8 +411,9 @@ def test_deviation_row_kernel_bitwise(shape, mu):
     in registers along the march) leaves the same state, bit for bit, as the
     per-cell gather kernel: every 16-bit format, sources spread over many
     tiles and planes, mu, ragged rows and tiles, one-row and one-plane boxes,
-    rows up to the 1024-cell limit (two rows per tile), chunk lengths and
-    block orders (tiles dealt to the XCDs in turn, in runs, in ranges)."""
+    rows up to the 1024-cell limit (two rows per tile), rows per tile (cells
+    numbered through the tile's rows), chunk lengths and block orders (tiles
+    dealt to the XCDs in turn, in runs, in ranges)."""
     p = random_problem(3, shape, seed=sum(shape) + 51, mu=mu, nsteps=23)
     for prec in LOWP:
         ref = gpu_run(p, 23, prec, env={"LBEM_DEV3Z": 0})
@@ -421,7 +422,8 @@ def test_deviation_row_kernel_bitwise(shape, mu):
         for env in ({"LBEM_DEV3Z": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_LZ": 3, "LBEM_DEV3R_XCD": 0},
                     {"LBEM_DEV3Z": 1, "LBEM_DEV3R_LZ": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_NT": 512},
                     {"LBEM_DEV3Z": 1, "LBEM_DEV3R_NT": 256, "LBEM_DEV3R_LZ": 2},
-                    {"LBEM_DEV3Z": 1, "LBEM_DEV3R_XCD": 3, "LBEM_DEV3R_LZ": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_XCD": 1}):
+                    {"LBEM_DEV3Z": 1, "LBEM_DEV3R_XCD": 3, "LBEM_DEV3R_LZ": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_XCD": 1},
+                    {"LBEM_DEV3Z": 1, "LBEM_DEV3R_TY": 1}, {"LBEM_DEV3Z": 1, "LBEM_DEV3R_TY": 3, "LBEM_DEV3R_LZ": 5}):
             announce(f"row kernel {shape} mu={mu} {prec} {env}")
             s = gpu_run(p, 23, prec, env=dict(env, LBEM_DEV3R=1))
             got = s.get_state()

@@ -160,11 +160,11 @@ def test_batch_with_sources_mu_and_every_format_bitwise(graph):
 ROW_SETS = {
     "rows": [((32, 32, 12), "f16dev", False, False), ((9, 30, 10), "f16dev", True, False),
              ((33, 7, 5), "f16dev", True, False), ((128, 9, 1), "f16ghost", False, False),
-             ((512, 2, 3), "f16ghost", True, False), ((40, 1, 12), "f16ghost", True, False),
+             ((1024, 2, 3), "f16ghost", True, False), ((40, 1, 12), "f16ghost", True, False),
              ((96, 20, 17), "bf16dev", True, False), ((17, 5, 9), "bf16ghost", False, False)],
     "rows_mu": [((24, 10, 9), "f16dev", True, True), ((33, 7, 5), "f16ghost", True, True),
                 ((64, 3, 3), "bf16ghost", False, True), ((20, 12, 9), "f16ghost", False, True)],
-    "cells": [((520, 3, 4), "f16dev", True, True), ((32, 8, 8), "f16dev", False, False),
+    "cells": [((1040, 2, 3), "f16dev", True, True), ((32, 8, 8), "f16dev", False, False),
               ((20, 12, 9), "f16ghost", True, True), ((16, 16, 10), "f16ghost", True, False)],
 }
 
@@ -172,9 +172,10 @@ ROW_SETS = {
 @pytest.mark.parametrize("which", list(ROW_SETS))
 def test_batched_row_tiles_bitwise(which):
     """3D deviation members on the batch's whole-row tiling (two cells per
-    thread, ceil(nx/2) threads per row), with the row kernel forced on for
-    every class that qualifies: short, odd and single rows, tiles taller than
-    the box, one plane, chunks longer than the box, rows of exactly 2 NT cells;
+    thread, numbered through the tile's rows), with the row kernel forced on
+    for every class that qualifies: short, odd and single rows, tiles taller
+    than the box, one plane, chunks longer than the box, rows of exactly 1024
+    cells (two per thread of a 512-thread block);
     first steps from the natural layout, members that ran solo steps before
     they joined, sources and mu; and classes that fall back to the per-cell
     tiles.  Each member equals its solo run bit for bit."""
