@@ -87,7 +87,7 @@ typedef enum {
 /* Streaming pattern (eq. STREAM) of the stored populations. */
 typedef enum {
     LBEM_STREAM_AUTO = 0, /* pull (the multi-step fused kernels need two copies),
-                             except 3D F64, and 3D F32 below 3.5e6 cells, which
+                             except 3D F64, and 3D F32 below 1e6 cells, which
                              run single steps and take AA                       */
     LBEM_STREAM_PULL = 1, /* two copies; each step gathers from x - c_i           */
     LBEM_STREAM_AA = 2    /* one copy updated in place, alternating even/odd steps

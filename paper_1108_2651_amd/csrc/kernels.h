@@ -878,16 +878,15 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // NTS: streaming stores (the frame loads stay plain: neighbouring tiles share
 // them).  TH: tau = 1/2 known when compiling, as for the 2D kernel.
 template <typename T, int TX, int TY, bool MU, bool NTS, bool TH>
-__global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
+__global__ __launch_bounds__(TX * TY, TX * TY >= 512 ? 4 : 1) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g, const int lz,
                                                     const FusedSrc<T> fs, const AmpPack<T, 2> amps,
                                                     const T omega, const int tau_half)
 {
     constexpr int D = 3, Q = 7, P = 3;
-    constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;
-    static_assert(TC == NT, "one tile cell per thread");
+    constexpr int W = TX + 2, HH = TY + 2, FC = W * HH, TC = TX * TY;   // one tile cell per thread
     constexpr int NIP = 5;                       // in-plane velocities 0, +x, +y, -x, -y
-    constexpr int CF = (FC + NT - 1) / NT;       // frame cells per thread
+    constexpr int CF = (FC + TC - 1) / TC;       // frame cells per thread
     __shared__ T lin[NIP * P][FC];               // in-plane outputs of plane zz-1 (frame)
     __shared__ T lpz[3][P][TC];
     __shared__ T lmz[P][TC];
@@ -917,9 +916,9 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
         int gz = zz % g.nz;
         if (gz < 0) gz += g.nz;
         if (has_src) {
-            for (int k = threadIdx.x; k < P * FC; k += NT) (&lsrc[bi][0][0])[k] = T(0);
+            for (int k = threadIdx.x; k < P * FC; k += TC) (&lsrc[bi][0][0])[k] = T(0);
             __syncthreads();
-            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+            for (int k = s0 + threadIdx.x; k < s1; k += TC) {
                 const int2 e = fs.ent[k];          // x = plane offset * FC + frame cell, y = pair
                 if (e.x / FC == rel) lsrc[bi][e.y][e.x % FC] = fs.val[k];
             }
@@ -930,7 +929,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
         T held[CF][NIP * P];
 #pragma unroll
         for (int j = 0; j < CF; ++j) {
-            const int k = threadIdx.x + j * NT;
+            const int k = threadIdx.x + j * TC;
             if (k >= FC) continue;
             const int hx = k % W, hy = k / W;
             int gx = (x0 - 1 + hx) % g.nx, gy = (y0 - 1 + hy) % g.ny;
@@ -1014,7 +1013,7 @@ __global__ __launch_bounds__(NT) void k_step_fused3d(const T* src, T* dst, const
         // next iteration's step 2, after its step-1 barrier)
 #pragma unroll
         for (int j = 0; j < CF; ++j) {
-            const int k = threadIdx.x + j * NT;
+            const int k = threadIdx.x + j * TC;
             if (k >= FC) continue;
 #pragma unroll
             for (int q = 0; q < NIP * P; ++q) lin[q][k] = held[j][q];

@@ -64,12 +64,17 @@ bool valid_cfg(const lbem_config* c)
     return true;
 }
 
-// Below this many cells (about 152^3) a 3D state is served from the Infinity
-// Cache, where the 3D z-marching kernels cannot fill the chip and single
-// per-cell steps are as fast or faster.  Measured per update: FP32 fused pair
-// against single AA steps 144^3 35.1k / 36.1k MLUPS, 160^3 38.6k / 31.0k,
-// 176^3 37.6k / 24.5k; FP16 ghost row tiles against per-cell tiles 128^3
-// 36.6k / 43.3k, 144^3 30.9k / 24.5k, 160^3 33.2k / 26.9k.
+// 3D FP32 runs two fused steps per launch from this many cells on (about
+// 100^3), single AA steps below, where the state is Infinity-Cache resident
+// and the pair's tiles cannot fill the chip.  Measured, us per step, fused
+// pair (64 x 8 tiles) against single AA steps: 64^3 20.6 / 7.2, 80^3 23.6 /
+// 15.1, 96^3 23.8 / 24.3, 112^3 29.7 / 37.5, 128^3 47.4 / 58.5, 144^3 76.1 /
+// 82.5, 160^3 96.0 / 133.1.
+constexpr double FUSE3D_MIN = 1.0e6;
+// The column-tile z-march of the 16-bit formats (rows longer than the row
+// tiles take) from this many cells on (measured when it was the only 16-bit
+// z-march: FP16 ghost against per-cell tiles 144^3 30.9k / 24.5k MLUPS, 128^3
+// 36.6k / 43.3k).
 constexpr double SMALL3D = 3.5e6;
 // The 3D 16-bit formats take the whole-row tiles once the state one step
 // touches (stored values read and written, c_L^2 read: 112 B per cell with
@@ -88,7 +93,7 @@ int resolve_streaming(const lbem_config* c)
     // in-place AA pattern (half the memory) is as fast or faster.
     if (c->streaming != LBEM_STREAM_AUTO) return c->streaming;
     const double n = (double)c->nx * (double)c->ny * (double)c->nz;
-    if (c->dim == 3 && (c->prec == LBEM_F64 || (c->prec == LBEM_F32 && n < SMALL3D))) return LBEM_STREAM_AA;
+    if (c->dim == 3 && (c->prec == LBEM_F64 || (c->prec == LBEM_F32 && n < FUSE3D_MIN))) return LBEM_STREAM_AA;
     return LBEM_STREAM_PULL;
 }
 
@@ -390,11 +395,11 @@ static hipError_t go_fused3_t(lbem_s* h, const T* src, T* dst, const double* amp
     for (int j = 0; j < 2; ++j) a.a[j] = (T)(amp ? amp[j] : 0.0);
     // tau = 1/2 folded at compile time (4.5 % at 256^3), other tau general
     if (h->cfg.tau == 0.5)
-        hipLaunchKernelGGL((k_step_fused3d<T, TX, TY, MU, NTS, true>), dim3(h->fgeo.nblocks), dim3(NT), 0,
+        hipLaunchKernelGGL((k_step_fused3d<T, TX, TY, MU, NTS, true>), dim3(h->fgeo.nblocks), dim3(TX * TY), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, h->f3_lz, fs, a,
                            (T)(1.0 / h->cfg.tau), 1);
     else
-        hipLaunchKernelGGL((k_step_fused3d<T, TX, TY, MU, NTS, false>), dim3(h->fgeo.nblocks), dim3(NT), 0,
+        hipLaunchKernelGGL((k_step_fused3d<T, TX, TY, MU, NTS, false>), dim3(h->fgeo.nblocks), dim3(TX * TY), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, h->f3_lz, fs, a,
                            (T)(1.0 / h->cfg.tau), 0);
     return hipGetLastError();
@@ -403,6 +408,12 @@ static hipError_t go_fused3_t(lbem_s* h, const T* src, T* dst, const double* amp
 template <typename T, bool NTS>
 static hipError_t go_fused3_n(lbem_s* h, const T* src, T* dst, const double* amp)
 {
+    if constexpr (std::is_same<T, float>::value) {
+        if (h->f3_tx == 64 && h->f3_ty == 8) {
+            if (h->mu_set) return go_fused3_t<T, 64, 8, true, NTS>(h, src, dst, amp);
+            return go_fused3_t<T, 64, 8, false, NTS>(h, src, dst, amp);
+        }
+    }
     if (h->mu_set) {
         if (h->f3_tx == 64) return go_fused3_t<T, 64, 4, true, NTS>(h, src, dst, amp);
         return go_fused3_t<T, 32, 8, true, NTS>(h, src, dst, amp);
@@ -778,7 +789,7 @@ static void make_fused3_geo(lbem_s* h)
     // FP64 frames do not fit enough blocks per CU for the pair to pay off
     // (measured slower than single steps at 256^3), so FP64 runs single steps
     // unless asked for.
-    const bool small = (double)h->n < SMALL3D;
+    const bool small = (double)h->n < FUSE3D_MIN;
     h->fuse_ns = env_int("LBEM_FUSE3", (f64 || small) ? 1 : 2) == 2 ? 2 : 1;
     h->f3_tx = env_int("LBEM_FUSE3_TX", f64 ? 32 : 64) == 64 && !f64 ? 64 : 32;
     if (is_dev(h->prec)) {
@@ -787,6 +798,12 @@ static void make_fused3_geo(lbem_s* h)
         h->f3_tx = 64;
     }
     h->f3_ty = NT / h->f3_tx;
+    // FP32 64-wide tiles take 8 rows: 512 threads, two blocks per CU (80 KB of
+    // LDS, <= 128 VGPRs), and step 1 runs on a frame of 1.29x the tile instead
+    // of 1.55x.  Measured, us per step, 64x4 / 64x8 / 32x16: 512^3 2801 / 2508
+    // / 2663, 384^3 1219 / 1103 / 1233, 256^3 348 / 307 / 332, 192^3 167 / 150
+    // / 161.  LBEM_FUSE3_TY=4 keeps the 256-thread tiles.
+    if (h->prec == LBEM_F32 && h->f3_tx == 64 && env_int("LBEM_FUSE3_TY", 8) == 8) h->f3_ty = 8;
     Geo& g = h->fgeo;
     g = h->geo;
     g.tiles_x = (g.nx + h->f3_tx - 1) / h->f3_tx;

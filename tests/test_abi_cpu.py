@@ -37,7 +37,7 @@ def test_strerror_and_required_bytes():
     assert 2 * 5 * 4 * n + 4 * n + 24 * n <= b <= 2 * 5 * 4 * n + 4 * n + 24 * n + 4 * 256
     # the default is pull (two copies: the fused multi-step kernels need them);
     # the in-place AA pattern keeps one copy of the 21 populations, and is the
-    # default for 3D FP64 and for 3D FP32 boxes below 3.5e6 cells
+    # default for 3D FP64 and for 3D FP32 boxes below 1e6 cells
     b3 = lbem.required_bytes(3, (256, 256, 256), "f32")
     assert b3 == lbem.required_bytes(3, (256, 256, 256), "f32", streaming="pull")
     assert lbem.required_bytes(3, (256, 256, 256), "f32", streaming="aa") < b3

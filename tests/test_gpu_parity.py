@@ -149,13 +149,15 @@ def test_temporal_blocking_bitwise(prec, shape, mu):
 @pytest.mark.parametrize("shape", [(40, 24, 20), (70, 9, 5), (33, 17, 37), (5, 3, 7), (128, 4, 2)])
 def test_temporal_blocking_3d_bitwise(prec, shape, mu):
     """Two fused 3D steps per launch (z-marching, LDS plane rings, sources
-    with periodic images, mu-gradient source) equal two single steps bit for
-    bit."""
+    with periodic images, mu-gradient source; 64x4, 32x8 and, in FP32, 64x8
+    column tiles) equal two single steps bit for bit."""
     p = random_problem(3, shape, seed=sum(shape) + 13, mu=mu, nsteps=31)
     ref = gpu_run(p, 31, prec, "pull", env={"LBEM_FUSE3": 1}).moments()
     combos = [dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=32), dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=3),
               dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=1),
-              dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=3)]
+              dict(LBEM_FUSE3_TX=32, LBEM_FUSE3_LZ=1, LBEM_FUSE3_XCD=3),
+              dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_TY=4, LBEM_FUSE3_LZ=32),
+              dict(LBEM_FUSE3_TX=64, LBEM_FUSE3_TY=4, LBEM_FUSE3_LZ=2, LBEM_FUSE3_XCD=3)]
     for env in combos:
         env["LBEM_FUSE3"] = 2
         announce(f"fused3d {prec} {shape} {env}")
