@@ -43,6 +43,10 @@ def test_strerror_and_required_bytes():
     assert lbem.required_bytes(3, (256, 256, 256), "f32", streaming="aa") < b3
     small = lbem.required_bytes(3, (64, 64, 64), "f32")
     assert small == lbem.required_bytes(3, (64, 64, 64), "f32", streaming="aa")
+    # the boundary: 96^3 (0.88e6 cells) still AA, 112^3 (1.4e6) pull for the fused pair
+    assert lbem.required_bytes(3, (96, 96, 96), "f32") == lbem.required_bytes(3, (96, 96, 96), "f32", streaming="aa")
+    assert lbem.required_bytes(3, (112, 112, 112), "f32") == \
+        lbem.required_bytes(3, (112, 112, 112), "f32", streaming="pull")
     assert lbem.required_bytes(3, (256, 256, 256), "f64") == \
         lbem.required_bytes(3, (256, 256, 256), "f64", streaming="aa")
     assert lbem.required_bytes(2, (64, 64, 1), "f64") == lbem.required_bytes(2, (64, 64, 1), "f64", streaming="pull")

@@ -1,5 +1,7 @@
-"""Error paths of the C ABI on a GPU (all conditions forced from the host; no
-kernel is made to fault)."""
+"""Error paths and default choices of the C ABI on a GPU (error conditions forced
+from the host; no kernel is made to fault)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -92,3 +94,30 @@ def test_rows_longer_than_the_row_kernels(dim, shape):
         E, B = s.moments()
         assert np.isfinite(E).all() and np.isfinite(B).all()
         s.close()
+
+
+@pytest.mark.parametrize("shape,spl", [((96, 96, 96), 1), ((112, 112, 112), 2), ((128, 64, 160), 2)])
+def test_3d_fp32_size_policy(shape, spl):
+    """3D FP32 with automatic streaming runs single AA steps below 1e6 cells
+    (Infinity-Cache resident: the fused pair cannot fill the chip) and two
+    fused steps per launch from there on; the pair's result equals single
+    steps bit for bit."""
+    announce(f"fp32 size policy {shape}")
+    p = random_problem(3, shape, seed=sum(shape), nsteps=4)
+    s = lbem.Solver(3, shape, "f32")
+    assert s.steps_per_launch == spl
+    s.setup(p)
+    s.step(4, p.amp[:4])
+    got = s.moments()
+    s.close()
+    os.environ["LBEM_FUSE3"] = "1"
+    try:
+        r = lbem.Solver(3, shape, "f32", streaming="pull")
+    finally:
+        os.environ.pop("LBEM_FUSE3", None)
+    assert r.steps_per_launch == 1
+    r.setup(p)
+    r.step(4, p.amp[:4])
+    want = r.moments()
+    r.close()
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
