@@ -866,17 +866,20 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
 // ---------------------------------------------------------------------------
 // 3D temporal blocking: two time steps per launch, marching along z
 // ---------------------------------------------------------------------------
-// A block owns a TX x TY column tile and a chunk of lz planes.  For every
+// A block of TX x TY threads owns a TX x TY column tile and a chunk of lz
+// planes.  For every
 // plane zz from z0-1 to z0+lz it runs step 1 on the tile grown by one cell in
 // x and y (pulling the stored state from HBM), keeping for tile cells the +z
 // components (LDS ring of 3 planes) and -z components (one plane) and holding
 // the in-plane components (rest, +-x, +-y, halo included) in registers; then
 // it runs step 2 on plane zz-1 of the tile, pulling from LDS, writes it, and
 // only then stores plane zz's in-plane components into the single LDS frame
-// (one frame instead of two keeps three blocks per CU).  Every update is the
-// same collide() as the single-step kernel: bit-identical.
+// (one frame instead of two: three 64 x 4 blocks or two 64 x 8 blocks per CU).
+// Every update is the same collide() as the single-step kernel: bit-identical.
 // NTS: streaming stores (the frame loads stay plain: neighbouring tiles share
-// them).  TH: tau = 1/2 known when compiling, as for the 2D kernel.
+// them).  TH: tau = 1/2 known when compiling, as for the 2D kernel.  Tiles
+// of 512 threads ask for four waves per SIMD (<= 128 VGPRs), so that two
+// blocks share a CU; 256-thread tiles keep the compiler's choice.
 template <typename T, int TX, int TY, bool MU, bool NTS, bool TH>
 __global__ __launch_bounds__(TX * TY, TX * TY >= 512 ? 4 : 1) void k_step_fused3d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g, const int lz,
