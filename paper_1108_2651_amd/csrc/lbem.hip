@@ -72,9 +72,9 @@ bool valid_cfg(const lbem_config* c)
 // 82.5, 160^3 96.0 / 133.1.
 constexpr double FUSE3D_MIN = 1.0e6;
 // The column-tile z-march of the 16-bit formats (rows longer than the row
-// tiles take) from this many cells on (measured when it was the only 16-bit
-// z-march: FP16 ghost against per-cell tiles 144^3 30.9k / 24.5k MLUPS, 128^3
-// 36.6k / 43.3k).
+// tiles take) from this many cells on: the cache-residency threshold every 3D
+// z-marching kernel shared before the row tiles and the 64 x 8 FP32 pair got
+// their own, kept for these rare shapes (not re-measured).
 constexpr double SMALL3D = 3.5e6;
 // The 3D 16-bit formats take the whole-row tiles once the state one step
 // touches (stored values read and written, c_L^2 read: 112 B per cell with
