@@ -712,8 +712,8 @@ struct AmpPack {
 // NTS: streaming stores of the state (lattices beyond the last-level cache).
 // TH: tau = 1/2 known when compiling (the reflection collision, whatever
 // tau_half says), else tau_half chooses at run time.
-template <typename T, int NS, int TY, bool MU, bool O32, bool NTS, bool TH>
-__global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
+template <typename T, int NS, int TY, bool MU, bool O32, bool NTS, bool TH, int NTB = NT>
+__global__ __launch_bounds__(NTB) void k_step_fused2d(const T* src, T* dst, const T* __restrict__ cl2a,
                                                     const T* __restrict__ dlnmu, const Geo g,
                                                     const FusedSrc<T> fs, const AmpPack<T, NS> amps,
                                                     const T omega, const int tau_half)
@@ -739,9 +739,9 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         const int s0 = fs.off[b], s1 = fs.off[b + 1];
         if (s1 > s0) {
             has_src = true;
-            for (int k = threadIdx.x; k < FC; k += NT) ls[k] = T(0);
+            for (int k = threadIdx.x; k < FC; k += NTB) ls[k] = T(0);
             __syncthreads();
-            for (int k = s0 + threadIdx.x; k < s1; k += NT) {
+            for (int k = s0 + threadIdx.x; k < s1; k += NTB) {
                 const int2 e = fs.ent[k];
                 ls[e.x] = fs.val[k];
             }
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
     // step 1 over the whole frame: every thread first issues the HBM loads of
     // all its frame cells, then collides them into LDS layer 0
     {
-        constexpr int C0 = (FC + NT - 1) / NT;
+        constexpr int C0 = (FC + NTB - 1) / NTB;
         T fv0[C0][Q][1];
         T cl0[C0];
         T dl0[C0][2];
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         const bool wide = g.nx >= W && g.ny >= FH;
 #pragma unroll
         for (int j = 0; j < C0; ++j) {
-            const int k = threadIdx.x + j * NT;
+            const int k = threadIdx.x + j * NTB;
             if (k < FC) {
                 const int fx = k % W, fy = k / W;
                 int gx = x0 + fx, gy = y0 + fy;
@@ -798,7 +798,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         const T amp = has_src ? amps.a[0] : T(0);
 #pragma unroll
         for (int j = 0; j < C0; ++j) {
-            const int k = threadIdx.x + j * NT;
+            const int k = threadIdx.x + j * NTB;
             if (k < FC) {
                 T rho[1], K[2], Sp[1], o[Q][1];
                 moments<2, T>(fv0[j], rho, K);
@@ -824,7 +824,7 @@ __global__ __launch_bounds__(NT) void k_step_fused2d(const T* src, T* dst, const
         const int wr = TXF + 2 * r, hr = TY + 2 * r, off = H - r;
         const T amp = has_src ? amps.a[st] : T(0);
         const int in = (st - 1) % NB, out = st % NB;
-        for (int k = threadIdx.x; k < wr * hr; k += NT) {
+        for (int k = threadIdx.x; k < wr * hr; k += NTB) {
             const int fx = off + k % wr, fy = off + k / wr;
             const int f = fy * W + fx;
             T fv[Q][1];

@@ -152,7 +152,7 @@ struct lbem_s {
     int vec;
     // temporal blocking (fuse_ns steps per launch; 1 = off): 2D tiles 64 x fuse_ty,
     // 3D column tiles f3_tx x f3_ty marching over chunks of f3_lz planes
-    int fuse_ns, fuse_ty;
+    int fuse_ns, fuse_ty, fuse_nt;
     int f3_tx, f3_ty, f3_lz;
     Geo fgeo;
     int* fsrc_off;
@@ -326,19 +326,19 @@ static hipError_t launch_fields(lbem_s* h, const R& rd, double* E, double* B, do
 // The paper's tau = 1/2 gets its own instantiation: the reflection collision
 // folds at compile time (measured 2 % faster at 2048^2, 12 % at 8192^2 with
 // four steps per launch); other tau take the general one.
-template <typename T, int NS, int TY, bool MU, bool O32, bool NTS>
+template <typename T, int NS, int TY, bool MU, bool O32, bool NTS, int NTB>
 static void launch_fused2d(lbem_s* h, const T* src, T* dst, const FusedSrc<T>& fs, const AmpPack<T, NS>& a)
 {
     const T om = (T)(1.0 / h->cfg.tau);
     if (h->cfg.tau == 0.5)
-        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, O32, NTS, true>), dim3(h->fgeo.nblocks), dim3(NT), 0,
+        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, O32, NTS, true, NTB>), dim3(h->fgeo.nblocks), dim3(NTB), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, om, 1);
     else
-        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, O32, NTS, false>), dim3(h->fgeo.nblocks), dim3(NT), 0,
+        hipLaunchKernelGGL((k_step_fused2d<T, NS, TY, MU, O32, NTS, false, NTB>), dim3(h->fgeo.nblocks), dim3(NTB), 0,
                            h->stream, src, dst, (const T*)h->cl2, (const T*)h->dlnmu, h->fgeo, fs, a, om, 0);
 }
 
-template <typename T, int NS, int TY, bool MU>
+template <typename T, int NS, int TY, bool MU, int NTB>
 static hipError_t go_fused_ntm(lbem_s* h, const T* src, T* dst, const double* amp)
 {
     FusedSrc<T> fs;
@@ -350,19 +350,19 @@ static hipError_t go_fused_ntm(lbem_s* h, const T* src, T* dst, const double* am
     // 32-bit element offsets while one population plane fits 2^32 bytes;
     // streaming stores beyond the last-level cache (2-3 % there)
     if ((uint64_t)h->n * sizeof(T) <= (1ull << 32) && h->nts)
-        launch_fused2d<T, NS, TY, MU, true, true>(h, src, dst, fs, a);
+        launch_fused2d<T, NS, TY, MU, true, true, NTB>(h, src, dst, fs, a);
     else if ((uint64_t)h->n * sizeof(T) <= (1ull << 32))
-        launch_fused2d<T, NS, TY, MU, true, false>(h, src, dst, fs, a);
+        launch_fused2d<T, NS, TY, MU, true, false, NTB>(h, src, dst, fs, a);
     else
-        launch_fused2d<T, NS, TY, MU, false, false>(h, src, dst, fs, a);
+        launch_fused2d<T, NS, TY, MU, false, false, NTB>(h, src, dst, fs, a);
     return hipGetLastError();
 }
 
-template <typename T, int NS, int TY>
+template <typename T, int NS, int TY, int NTB = NT>
 static hipError_t go_fused_nt(lbem_s* h, const T* src, T* dst, const double* amp)
 {
-    if (h->mu_set) return go_fused_ntm<T, NS, TY, true>(h, src, dst, amp);
-    return go_fused_ntm<T, NS, TY, false>(h, src, dst, amp);
+    if (h->mu_set) return go_fused_ntm<T, NS, TY, true, NTB>(h, src, dst, amp);
+    return go_fused_ntm<T, NS, TY, false, NTB>(h, src, dst, amp);
 }
 
 template <typename T>
@@ -370,6 +370,11 @@ static hipError_t go_fused(lbem_s* h, const T* src, T* dst, const double* amp)
 {
     const int ns = h->fuse_ns, ty = h->fuse_ty;
     if constexpr (sizeof(T) == 4) {
+        if (h->fuse_nt == 512) {
+            if (ns == 2 && ty == 16) return go_fused_nt<T, 2, 16, 512>(h, src, dst, amp);
+            if (ns == 2 && ty == 32) return go_fused_nt<T, 2, 32, 512>(h, src, dst, amp);
+            if (ns == 4 && ty == 16) return go_fused_nt<T, 4, 16, 512>(h, src, dst, amp);
+        }
         if (ns == 2 && ty == 16) return go_fused_nt<T, 2, 16>(h, src, dst, amp);
         if (ns == 2 && ty == 8) return go_fused_nt<T, 2, 8>(h, src, dst, amp);
         if (ns == 2 && ty == 4) return go_fused_nt<T, 2, 4>(h, src, dst, amp);
@@ -823,20 +828,29 @@ static void make_fused3_geo(lbem_s* h)
 
 static void make_fused_geo(lbem_s* h)
 {
+    h->fuse_nt = 256;
     if (h->D == 3) {
         make_fused3_geo(h);
         return;
     }
     const bool f64 = h->prec == LBEM_F64;
-    // Two steps per pass while the double-buffered state fits the 256 MB
-    // Infinity Cache; beyond it (HBM-bound) four steps halve the traffic again.
-    const double state = (double)h->n * (f64 ? 88.0 : 44.0);
-    const bool big = !f64 && state > 256.0 * 1024 * 1024;
-    h->fuse_ns = env_int("LBEM_FUSE", big ? 4 : 2);
-    h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : 8);
-    // only the instantiated (steps, rows) pairs; anything else runs single steps
+    // FP32: four steps per pass on 64 x 16 tiles of 512 threads, at every size.
+    // Measured, us per step, (steps, rows, threads): 2048^2 (2, 8, 256) 13.49,
+    // (4, 8, 256) 13.23, (4, 16, 256) 13.29, (4, 16, 512) 10.49; 1024^2 5.13 /
+    // 4.61 / 4.44 / 3.72; 512^2 2.45 / 1.85 / 2.29 / 1.65; 128^2 2.06 / 1.59 /
+    // 2.12 / 1.48; 4096^2 80.4 / 59.6 / 56.4 / 50.3; 8192^2 296 / 223 / 210 /
+    // 185.  The 512-thread block halves the frame per tile cell of the
+    // 256-thread 64 x 16 tile at the same two cells per thread.  FP64: two
+    // steps on 64 x 4 tiles.
+    h->fuse_ns = env_int("LBEM_FUSE", f64 ? 2 : 4);
+    h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : 16);
+    // only the instantiated (steps, rows, threads) triples; anything else runs
+    // single steps.  The thread count follows the (steps, rows) pair unless set.
     const int ns = h->fuse_ns, ty = h->fuse_ty;
+    const bool pair512 = !f64 && ((ns == 2 && (ty == 16 || ty == 32)) || (ns == 4 && ty == 16));
+    h->fuse_nt = (!f64 && env_int("LBEM_FUSE_NT", pair512 ? 512 : 256) == 512) ? 512 : 256;
     const bool ok = f64 ? ((ns == 2 && (ty == 8 || ty == 4)) || (ns == 3 && ty == 8))
+                  : h->fuse_nt == 512 ? ((ns == 2 && (ty == 16 || ty == 32)) || (ns == 4 && ty == 16))
                         : ((ns == 2 && (ty == 16 || ty == 8 || ty == 4)) || (ns == 3 && ty == 16) ||
                            (ns == 4 && (ty == 16 || ty == 8)));
     if (!ok) h->fuse_ns = 1;

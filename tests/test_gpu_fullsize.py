@@ -54,7 +54,7 @@ def test_config2_full_grid_1000_steps_fp32():
     announce("config2 2048^2 fp32 full grid, 1000 steps (oracle on all host cores)")
     s = lbem.Solver(p.dim, p.shape, "f32", w0_vac=p.w0_vac)
     s.setup(p)
-    assert s.steps_per_launch == 2
+    assert s.steps_per_launch == 4
     s.step(k, p.amp[:k])
     Eg, Bg = s.moments()
     s.close()
@@ -75,7 +75,7 @@ def test_config2_recipe_5000_steps_fp32():
     announce("config2 recipe 512^2 fp32 full grid, 5000 steps (oracle on all host cores)")
     s = lbem.Solver(p.dim, p.shape, "f32", w0_vac=p.w0_vac)
     s.setup(p)
-    assert s.steps_per_launch == 2
+    assert s.steps_per_launch == 4
     s.step(k, p.amp[:k])
     Eg, Bg = s.moments()
     s.close()
@@ -86,9 +86,9 @@ def test_config2_recipe_5000_steps_fp32():
 
 
 def test_config2_full_2048_fp32_fused():
-    """The benchmark's primary workload and launch configuration (2048^2
-    FP32, two time steps per launch), 64 steps, 6 sampled cells including
-    the source line and the periodic seams."""
+    """The config-2 workload in its launch configuration (2048^2 FP32, four
+    time steps per launch on 512-thread tiles), 64 steps, 6 sampled cells
+    including the source line and the periodic seams."""
     k = 64
     p = inputs.config2(nsteps=k)
     announce("config2 2048^2 fp32 full size")

@@ -130,18 +130,20 @@ def test_ragged_shapes_all_terms(dim, shape, mu):
 @pytest.mark.parametrize("shape", [(96, 40, 1), (100, 37, 1), (1, 64, 1), (300, 2, 1), (130, 70, 1)])
 def test_temporal_blocking_bitwise(prec, shape, mu):
     """2, 3 or 4 fused time steps per launch (LDS frame with halo, periodic
-    images of sources included, with or without the mu-gradient source)
-    equal the same number of single steps bit for bit, for ragged and tiny
-    lattices and odd step counts."""
+    images of sources included, with or without the mu-gradient source; 256-
+    and, in FP32, 512-thread tiles) equal the same number of single steps bit
+    for bit, for ragged and tiny lattices and odd step counts."""
     p = random_problem(2, shape, seed=sum(shape) + 11, mu=mu, nsteps=53)
     ref = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": 1}).moments()
-    combos = [(2, 16), (2, 8), (2, 4), (3, 16), (4, 16), (4, 8)] if prec == "f32" else [(2, 8), (2, 4), (3, 8)]
-    for ns, ty in combos:
-        announce(f"fused {prec} {shape} ns={ns} ty={ty}")
-        s = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": ns, "LBEM_FUSE_TY": ty})
+    combos = ([(2, 16, 256), (2, 8, 256), (2, 4, 256), (3, 16, 256), (4, 16, 256), (4, 8, 256),
+               (2, 16, 512), (2, 32, 512), (4, 16, 512)] if prec == "f32"
+              else [(2, 8, 256), (2, 4, 256), (3, 8, 256)])
+    for ns, ty, nt in combos:
+        announce(f"fused {prec} {shape} ns={ns} ty={ty} threads={nt}")
+        s = gpu_run(p, 53, prec, "pull", env={"LBEM_FUSE": ns, "LBEM_FUSE_TY": ty, "LBEM_FUSE_NT": nt})
         assert s.steps_per_launch == ns
         got = s.moments()
-        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (ns, ty)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (ns, ty, nt)
 
 
 @pytest.mark.parametrize("mu", [False, True])
