@@ -840,10 +840,14 @@ static void make_fused_geo(lbem_s* h)
     // 4.61 / 4.44 / 3.72; 512^2 2.45 / 1.85 / 2.29 / 1.65; 128^2 2.06 / 1.59 /
     // 2.12 / 1.48; 4096^2 80.4 / 59.6 / 56.4 / 50.3; 8192^2 296 / 223 / 210 /
     // 185.  The 512-thread block halves the frame per tile cell of the
-    // 256-thread 64 x 16 tile at the same two cells per thread.  FP64: two
-    // steps on 64 x 4 tiles.
-    h->fuse_ns = env_int("LBEM_FUSE", f64 ? 2 : 4);
-    h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : 16);
+    // 256-thread 64 x 16 tile at the same two cells per thread.  With a varying
+    // mu the frame also stages grad ln mu, and the four-step 512-thread tile
+    // (86 KB of LDS) leaves one block per CU: two steps on 64 x 8 tiles there
+    // (2048^2, us per step: (2, 8, 256) 16.02, (2, 16, 512) 15.95, (4, 8, 256)
+    // 19.36, (4, 16, 512) 18.73).  FP64: two steps on 64 x 4 tiles.
+    const bool muv = h->cfg.mu_varies != 0;
+    h->fuse_ns = env_int("LBEM_FUSE", (f64 || muv) ? 2 : 4);
+    h->fuse_ty = env_int("LBEM_FUSE_TY", f64 ? 4 : (muv ? 8 : 16));
     // only the instantiated (steps, rows, threads) triples; anything else runs
     // single steps.  The thread count follows the (steps, rows) pair unless set.
     const int ns = h->fuse_ns, ty = h->fuse_ty;
