@@ -488,7 +488,9 @@ def main():
             try:
                 r = run_workload(name, prec, k, w, st, p=make_problem(name, nprob if name == "c4" else 1100))
                 if name == "c2":
-                    r["note"] = "2048^2 state (101-185 MB) fits the 256 MB Infinity Cache: not an HBM point"
+                    r["note"] = ("2048^2 state (101-185 MB) fits the 256 MB Infinity Cache: not an HBM point; "
+                                 "the FP32 pull default runs four steps per launch and is bound by vector-ALU "
+                                 "issue (0.69 of the VALU issue slots, profiles/k_step_stream_collide.md)")
                 variants.append(r)
             except Exception as e:  # report, do not hide
                 variants.append(dict(workload=name, prec=prec, streaming=st, error=str(e)))
